@@ -1,0 +1,192 @@
+"""Benchmark: batched mixed-precision Kronecker CG on one MI355X.
+
+Workload (one step): solve A X = B for the 3-mode RBF Kronecker operator
+A = K1 (x) K2 (x) K3 + 0.01 I (64 points per mode, lengthscale 0.15,
+n = 262,144) with 32 right-hand sides N(0, 1), to a true relative residual
+of 1e-5 per right-hand side: CG in FP32 (FP32 MFMA mode contractions, FP64
+scalars and dot accumulation) inside FP64 iterative refinement.  Inputs are
+resident in HBM before the timed region; the operator is built once.
+
+Metric: RHS*iterations/s = inner CG iterations summed over right-hand sides
+(all refinement sweeps) divided by the wall time of the timed steps.
+
+Printed on one JSON line with:
+  roofline      the dominant kernel's algorithmic bytes per launch over its
+                average duration (HIP events on the launch stream, recorded
+                around every launch inside the timed region), against 8 TB/s;
+  cpu_baseline  the float64 oracle's CG on the same operator, timed on this
+                host's cores over a bounded window of iterations;
+  mixed_vs_fp64 time to 1e-6 true relative residual: mixed precision versus
+                plain FP64 CG on the GPU (outside the timed region).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Kron-CG RHS·iters/s + % roofline; mixed vs FP64 at 1e-6 rel residual"
+HBM_PEAK_GBS = 8000.0
+FP32_MFMA_PEAK_TFLOPS = 157.3
+
+# Algorithmic HBM bytes per element of one right-hand side, per launch class
+# (FP32 working vectors, 4 bytes per word):
+#   contract_rows : read r, p (direction formed on the fly), write T      3 words
+#   contract_mid  : read T, write T'                                        2 words
+#   contract_last : read T', r, p_old, write q, p_new                       5 words
+#   update        : read x, r, p, q, write x, r                             6 words
+BYTES_PER_ELEM = {"contract_rows": 12, "contract_mid": 8, "contract_last": 20, "update": 24}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--m", type=int, default=64, help="points per mode")
+    ap.add_argument("--nrhs", type=int, default=32)
+    ap.add_argument("--tol", type=float, default=1e-5)
+    ap.add_argument("--cpu-iters", type=int, default=40, help="oracle CG iterations timed on the host")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-tts", action="store_true", help="skip the mixed-vs-FP64 time-to-solution runs")
+    ap.add_argument("--autotune", action="store_true")
+    return ap.parse_args()
+
+
+def cpu_baseline(w, iters):
+    """The oracle's float64 CG (numpy) on the same operator: bounded window of iterations."""
+    from oracle import cg as ocg
+    from oracle import kron
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    s = w.systems[0]
+    B = w.B[0]
+    apply_A = lambda V: kron.mvm(s.factors, V, s.sigma2)
+    ocg.cg(apply_A, B[:, :], tol=1e-30, max_iters=2)             # warm caches / BLAS threads
+    t0 = time.perf_counter()
+    res = ocg.cg(apply_A, B, tol=1e-30, max_iters=iters)
+    dt = time.perf_counter() - t0
+    rhs_iters = int(res.iters.sum())
+    return {"value": rhs_iters / dt, "unit": "RHS*iters/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"numpy float64 CG on the same operator, {B.shape[0]} RHS x {iters} iterations "
+                      f"({rhs_iters} RHS*iters) in {dt:.2f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+    import workloads as wl
+    from paper_2309_03060_amd import KronOperator, SystemSpec, decode_info
+
+    dev = torch.device("cuda:0")
+    w = wl.config2(m=args.m, nrhs=args.nrhs)
+    s = w.systems[0]
+    nrhs = args.nrhs
+    n = s.n
+    spec = SystemSpec(factors=[[torch.tensor(f, device=dev) for f in s.factors[0]]], sigma2=s.sigma2)
+    op = KronOperator([spec], prec="fp32")
+    B = torch.tensor(w.B[0], device=dev).reshape(-1).contiguous()
+    if args.autotune:
+        op.autotune(nrhs)
+    opts = dict(tol=args.tol, max_iters=20000, prec="fp32", inner_tol=1e-4, max_sweeps=40, check_every=32)
+
+    for _ in range(args.warmup):
+        op.solve(B, nrhs, **opts)
+    torch.cuda.synchronize()
+
+    op.profile_enable(True)
+    infos = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        X, info = op.solve(B, nrhs, **opts)
+        infos.append(info)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    recs = [decode_info(i, nrhs) for i in infos]
+    rhs_iters = sum(r["iters"] for rec in recs for r in rec)
+    statuses = sorted({r["status"] for rec in recs for r in rec})
+    worst = max(r["relres"] for rec in recs for r in rec)
+    value = rhs_iters / dt
+
+    # per-kernel averages (HIP events around every launch in the timed region)
+    kern = {}
+    for name in BYTES_PER_ELEM:
+        ms, cnt = op.profile_read(name)
+        if cnt:
+            kern[name] = {"total_ms": ms, "launches": cnt, "avg_us": 1e3 * ms / cnt}
+    for name in ("contract_rows", "contract_mid", "contract_last"):
+        pass
+    op.profile_enable(False)
+    dom = max(kern, key=lambda k: kern[k]["total_ms"]) if kern else None
+    roof = None
+    if dom:
+        # every launch of a class processes the active RHS of that iteration; the summed
+        # active RHS over the region is the RHS*iterations count
+        alg_bytes = BYTES_PER_ELEM[dom] * n * rhs_iters
+        launches = kern[dom]["launches"]
+        per_launch = alg_bytes / launches
+        avg_s = kern[dom]["total_ms"] * 1e-3 / launches
+        achieved = per_launch / avg_s / 1e9
+        roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "bytes_per_launch": int(per_launch), "avg_launch_us": round(avg_s * 1e6, 2),
+                "per_kernel": {k: {"avg_us": round(v["avg_us"], 2), "launches": v["launches"],
+                                   "GB/s": round(BYTES_PER_ELEM[k] * n * rhs_iters / v["launches"] /
+                                                 (v["avg_us"] * 1e-6) / 1e9, 1)}
+                               for k, v in kern.items()}}
+
+    # mixed precision vs plain FP64 at 1e-6 true relative residual
+    tts = None
+    if not args.no_tts:
+        res = {}
+        for label, o in (("mixed_fp32_refined", dict(opts, tol=1e-6)),
+                         ("fp64_cg", dict(tol=1e-6, max_iters=20000, prec="fp64", check_every=32))):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            X, info = op.solve(B, nrhs, **o)
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t1
+            rec = decode_info(info, nrhs)
+            res[label] = {"seconds": round(t, 4), "iters_max": max(r["iters"] for r in rec),
+                          "relres_max": max(r["relres"] for r in rec),
+                          "status": sorted({r["status"] for r in rec})}
+        res["speedup"] = round(res["fp64_cg"]["seconds"] / res["mixed_fp32_refined"]["seconds"], 3)
+        res["note"] = ("fp64_cg relres is its recursive residual; mixed relres is the FP64 true residual")
+        tts = res
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(w, args.cpu_iters)
+
+    out = {
+        "metric": METRIC, "value": round(value, 1), "unit": "RHS*iters/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * dt / args.steps, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"K1(x)K2(x)K3+0.01I, RBF l=0.15 on {args.m} U[0,1] points per mode, "
+                               f"n={n}, {nrhs} RHS N(0,1), FP32 inner CG + FP64 refinement to true relres "
+                               f"{args.tol:g}", "n": n, "nrhs": nrhs, "factor_dim": args.m,
+                   "rhs_iters_per_step": rhs_iters // max(1, args.steps), "statuses": statuses,
+                   "worst_relres": worst, "parallelism": "single GPU"},
+        "roofline": roof, "cpu_baseline": cpu, "mixed_vs_fp64": tts,
+    }
+    print(json.dumps(out))
+    op.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,181 @@
+/*
+ * cola.h - C ABI of the MI355X (gfx950) sum-of-Kronecker conjugate-gradient library.
+ *
+ * Operator (CoLA, arxiv 2309.03060; Sec. 3.1 base operators Dense and Diagonal,
+ * Sec. 3.2 Sum and Kronecker compositions, Table 2 Kronecker MVM cost):
+ *
+ *     A = sum_{j<J} ( K_j1 (x) K_j2 [(x) K_j3] ) + diag(d) + sigma2 * I
+ *
+ * A is assumed symmetric positive definite, so solves use conjugate gradients
+ * (the PSD base case, Sec. 3.2 "Decoration/annotation operators" and App. C's
+ * table of base-case iterative methods).  Gradients follow the solve VJP of
+ * App. B.2 (autograd rule 1).
+ *
+ * Conventions used by every entry point
+ * -------------------------------------
+ *  - vec is row-major: the element of multi-index (i1, i2, i3) sits at
+ *    i1*n2*n3 + i2*n3 + i3, so (K1 (x) K2) x = vec(K1 X K2^T), X = x as n1 x n2.
+ *  - Factors are dense, row-major n_k x n_k, float64, in device memory.
+ *  - Vectors are packed: system s (n_s unknowns) with nrhs right-hand sides
+ *    occupies nrhs * n_s consecutive elements, right-hand side r of it at
+ *    offset r * n_s; systems follow each other in the order given at create.
+ *  - All device pointers must be 16-byte aligned and refer to memory on the
+ *    device that is current when the call is made.
+ *  - `stream` is a hipStream_t (NULL = the null stream).  Calls enqueue work on
+ *    it and return; outputs are valid once the stream has reached that point.
+ *    The solve entry points may also wait on the stream to poll convergence
+ *    (see cola_solve_opts.check_every).
+ *  - Return value: COLA_OK, or a negative error for invalid arguments, an
+ *    allocation failure or a HIP error.  Numerical outcomes (non-convergence,
+ *    breakdown, non-finite data) are reported per right-hand side in
+ *    cola_solve_info, not as the return value.
+ *  - Errors leave caller buffers in an unspecified state but never free or
+ *    retain them.  The library keeps no pointer to caller memory past a call.
+ *  - Thread safety: one op may be used by one host thread / stream at a time.
+ */
+#ifndef COLA_H
+#define COLA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes ---------------------------------------------------------- */
+#define COLA_OK                 0
+#define COLA_NOT_CONVERGED      1   /* max_iters / max_sweeps reached; x is the last iterate */
+#define COLA_STAGNATED          2   /* refinement stopped halving the residual twice in a row */
+#define COLA_ERR_INVALID_ARG  (-1)
+#define COLA_ERR_NOT_SPD      (-2)  /* CG breakdown: p^T A p <= 0 */
+#define COLA_ERR_NONFINITE    (-3)  /* NaN / Inf met in b or during the iteration */
+#define COLA_ERR_OOM          (-4)
+#define COLA_ERR_HIP          (-5)
+#define COLA_ERR_UNSUPPORTED  (-6)
+
+/* element types of caller vectors --------------------------------------- */
+#define COLA_F64 0
+#define COLA_F32 1
+
+/* working precision of the Kronecker MVM and of the inner CG vectors ----- */
+#define COLA_PREC_FP64   0   /* FP64 factors, FP64 MFMA, FP64 vectors             */
+#define COLA_PREC_FP32   1   /* FP32 factors, FP32 MFMA, FP32 vectors             */
+#define COLA_PREC_BF16   2   /* BF16 factors and operands, FP32 accumulation      */
+#define COLA_PREC_BF16X3 3   /* 3-way BF16 split of factors and operands (~FP32)  */
+
+typedef struct cola_op_s* cola_op_t;
+
+/* One independent SPD system.  `factors` is a HOST array of nterms*nfactors
+ * DEVICE pointers: factor k of term j at index j*nfactors + k, each n_k x n_k
+ * float64 row-major.  Every term has the same dims.  `diag` is a device
+ * pointer to n float64 values or NULL (no diagonal term besides sigma2). */
+typedef struct {
+    int32_t nterms;              /* J >= 1                          */
+    int32_t nfactors;            /* F in {1, 2, 3}                  */
+    int64_t dims[3];             /* n_1..n_F >= 1; unused entries ignored */
+    const void* const* factors;  /* host array of device pointers   */
+    const void* diag;            /* device pointer or NULL          */
+    double sigma2;               /* >= 0, finite                    */
+} cola_system_desc;
+
+/* Build an operator from nsys systems (Sec. 3.2: the Sum of Kronecker terms
+ * and the Diagonal is represented by its parts, never formed densely).
+ * The library copies the factors and diagonal into its own FP64 master copy
+ * and converts a working copy in precision `prec` (COLA_PREC_*).  Copies
+ * are enqueued on `stream`; the caller may free its buffers once the stream
+ * has passed this call.  On success *out receives the handle. */
+int32_t cola_op_create(const cola_system_desc* systems, int32_t nsys, int32_t prec,
+                       void* stream, cola_op_t* out);
+
+/* Release the operator and every device buffer it owns (synchronises the
+ * device first).  NULL is accepted. */
+int32_t cola_op_destroy(cola_op_t op);
+
+/* Total unknowns summed over systems (n_total) and number of systems. */
+int32_t cola_op_size(cola_op_t op, int64_t* n_total, int32_t* nsys);
+
+/* Y = A X (Sec. 3.2: MVM of the Sum = sum of the children's MVMs; each
+ * Kronecker term applied mode by mode at the Table 2 cost).  X and Y are
+ * packed vectors of nrhs right-hand sides, element type `dtype`:
+ *   prec == COLA_PREC_FP64            requires dtype == COLA_F64;
+ *   prec == the op's working precision requires dtype == COLA_F32.
+ * X and Y must not overlap. */
+int32_t cola_kron_matvec(cola_op_t op, const void* X, void* Y, int32_t nrhs,
+                         int32_t dtype, int32_t prec, void* stream);
+
+/* Solve options. */
+typedef struct {
+    double  tol;          /* target relative residual ||b - A x|| / ||b|| per RHS, > 0 */
+    int32_t max_iters;    /* max CG iterations per (inner) solve, >= 1                  */
+    int32_t prec;         /* COLA_PREC_FP64, or the op's working precision              */
+    double  inner_tol;    /* relative residual target of each inner solve (refinement)  */
+    int32_t max_sweeps;   /* refinement sweeps when prec != FP64 (>= 1); ignored for FP64 */
+    int32_t check_every;  /* >0: the host waits on the stream every this many CG
+                             iterations to stop early once all RHS converged;
+                             0: never wait - all work is enqueued (max_iters
+                             iterations per sweep, device-side early exit), which
+                             makes the call safe under stream capture           */
+} cola_solve_opts;
+
+/* Per (system, RHS) outcome, written to DEVICE memory in stream order. */
+typedef struct {
+    int32_t status;       /* COLA_OK, COLA_NOT_CONVERGED, COLA_STAGNATED,
+                             COLA_ERR_NOT_SPD or COLA_ERR_NONFINITE            */
+    int32_t iters;        /* CG iterations summed over all sweeps               */
+    int32_t sweeps;       /* refinement sweeps (0 for a plain solve)            */
+    int32_t reserved;
+    double  relres;       /* final relative residual: the FP64 true residual
+                             when refining, the recursive one for a plain solve */
+} cola_solve_info;
+
+/* Solve A X = B for nrhs right-hand sides (packed, float64, device).
+ *  - prec == COLA_PREC_FP64: textbook CG in FP64 to tol on the recursive
+ *    residual, x0 = 0.
+ *  - prec == the op's working precision: iterative refinement - the FP64
+ *    residual r = b - A x is formed with the FP64 factors; CG in the working
+ *    precision solves A d = r / ||r|| to inner_tol; x += ||r|| d in FP64;
+ *    stops when the FP64 relative residual <= tol.
+ * Right-hand sides converge independently; the call ends when all have
+ * converged or hit a limit (the multi-RHS semantics of the paper's block
+ * solves, App. D.5).  info: device array of nsys*nrhs entries, or NULL.
+ * The first call for a given nrhs allocates workspace (not capture-safe);
+ * later calls with nrhs no larger allocate nothing. */
+int32_t cola_cg_solve(cola_op_t op, const double* B, double* X, int32_t nrhs,
+                      const cola_solve_opts* opts, cola_solve_info* info, void* stream);
+
+/* Adjoint backward of X = A^{-1} B (App. B.2, rule 1).  Given X (the forward
+ * solution) and G = dL/dX (packed float64), computes
+ *     Lambda = A^{-1} G                     (= dL/dB), by a second solve,
+ *     dK_jk  = - sum_r Lambda_r,(k) Z_r,(k)^T  with Z_r = X_r multiplied along
+ *              every mode except k by term j's factors (mode-k unfoldings),
+ *     dd     = - sum_r lambda_r * x_r   (elementwise),
+ *     dsigma2= - sum_r lambda_r . x_r.
+ * dfactors: HOST array with one device pointer per (system, term, factor), in
+ * create order, each receiving an n_k x n_k float64 gradient (entry-wise,
+ * unsymmetrised); NULL skips factor gradients.  ddiag: HOST array of nsys
+ * device pointers (n_s float64 each; entries may be NULL), or NULL.
+ * dsigma2: device array of nsys doubles, or NULL.  info as for the solve. */
+int32_t cola_cg_solve_backward(cola_op_t op, const double* X, const double* G, int32_t nrhs,
+                               const cola_solve_opts* opts, double* Lambda,
+                               void* const* dfactors, void* const* ddiag, double* dsigma2,
+                               cola_solve_info* info, void* stream);
+
+/* Pick kernel tile shapes for this op and nrhs by timing the candidates on
+ * `stream` (synchronises it).  Optional: without it a fixed default is used. */
+int32_t cola_autotune(cola_op_t op, int32_t nrhs, void* stream);
+
+/* Per-kernel timing with HIP events recorded on the launch stream around
+ * every kernel of the named class ("contract", "contract_last", "update",
+ * "resident", ...).  enable != 0 starts collecting (and clears totals). */
+int32_t cola_profile_enable(cola_op_t op, int32_t enable);
+/* Totals since enable: summed milliseconds and launch count for `kernel`;
+ * synchronises the device.  Unknown names report zero launches. */
+int32_t cola_profile_read(cola_op_t op, const char* kernel, double* total_ms, int64_t* launches);
+
+/* Static description of a status code. */
+const char* cola_status_string(int32_t status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* COLA_H */

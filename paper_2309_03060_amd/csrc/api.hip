@@ -1,0 +1,607 @@
+// extern "C" entry points of libcola and the host-side drivers behind them.
+//
+// Everything numeric runs in the kernels of contract.hip / vector.hip /
+// grad.hip; this file validates arguments, owns device memory, plans the
+// per-mode passes of each Kronecker MVM and enqueues the CG and refinement
+// loops on the caller's stream.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "grad.h"
+#include "op.h"
+#include "vector.h"
+
+using namespace cola;
+
+namespace {
+
+#define HIP_TRY(expr)                                      \
+    do {                                                   \
+        hipError_t _e = (expr);                            \
+        if (_e != hipSuccess) return COLA_ERR_HIP;         \
+    } while (0)
+
+inline hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+int32_t alloc_bytes(void** p, size_t bytes) {
+    if (bytes == 0) bytes = 16;
+    if (hipMalloc(p, bytes) != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return COLA_ERR_OOM;
+    }
+    return COLA_OK;
+}
+
+void free_ws(Workspace& w) {
+    void* ptrs[] = {w.vx, w.vr, w.vp, w.vq, w.inter[0], w.inter[1], w.r64, w.partials,
+                    w.counters, w.cg, w.outer, w.cnt};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    if (w.host_flag) (void)hipHostFree(w.host_flag);
+    w = Workspace();
+}
+
+// Blocks per right-hand side of the widest reduction any kernel may use.
+int64_t max_blocks_per_rhs(const cola_op_s* op) {
+    int64_t m = 512;
+    for (const SysInfo& s : op->sys) {
+        const int64_t B = s.n / s.dims[0];
+        const int64_t b = ((B + 31) / 32) * ((s.dims[0] + 31) / 32);
+        m = std::max(m, b);
+        m = std::max<int64_t>(m, vec_blocks_per_rhs(s.n));
+    }
+    return m;
+}
+
+int32_t ensure_ws(cola_op_s* op, int nrhs, hipStream_t st) {
+    Workspace& w = op->ws;
+    if (w.nrhs >= nrhs) return COLA_OK;
+    free_ws(w);
+    const size_t vec = (size_t)nrhs * (size_t)op->nmax * sizeof(double);
+    int32_t rc = COLA_OK;
+    rc |= alloc_bytes(&w.vx, vec);
+    rc |= alloc_bytes(&w.vr, vec);
+    rc |= alloc_bytes(&w.vp, vec);
+    rc |= alloc_bytes(&w.vq, vec);
+    rc |= alloc_bytes(&w.inter[0], vec * op->Jmax);
+    rc |= alloc_bytes(&w.inter[1], vec * op->Jmax);
+    rc |= alloc_bytes((void**)&w.r64, vec);
+    w.part_stride = max_blocks_per_rhs(op);
+    rc |= alloc_bytes((void**)&w.partials, sizeof(double) * (size_t)nrhs * w.part_stride);
+    rc |= alloc_bytes((void**)&w.counters, sizeof(uint32_t) * (size_t)nrhs);
+    rc |= alloc_bytes((void**)&w.cg, sizeof(CgState) * (size_t)nrhs);
+    rc |= alloc_bytes((void**)&w.outer, sizeof(OuterState) * (size_t)nrhs);
+    rc |= alloc_bytes((void**)&w.cnt, sizeof(SolveCounters));
+    if (rc != COLA_OK) {
+        free_ws(w);
+        return COLA_ERR_OOM;
+    }
+    if (hipHostMalloc((void**)&w.host_flag, sizeof(int32_t) * 4, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        free_ws(w);
+        return COLA_ERR_OOM;
+    }
+    w.nrhs = nrhs;
+    HIP_TRY(fill_i32((int32_t*)w.counters, 0, nrhs, st));
+    HIP_TRY(fill_i32((int32_t*)w.cnt, 0, 2, st));
+    HIP_TRY(fill_i32((int32_t*)w.cg, 0, (int64_t)nrhs * sizeof(CgState) / 4, st));
+    HIP_TRY(fill_i32((int32_t*)w.outer, 0, (int64_t)nrhs * sizeof(OuterState) / 4, st));
+    return COLA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// tile choice: table entry (autotuned) or a size-based default
+TileCfg tile_for(const cola_op_s* op, int prec, bool rows, int64_t nk, int64_t B, int64_t g) {
+    auto it = op->tiles.find(PassKey{prec, rows ? 1 : 0, nk, B, g});
+    if (it != op->tiles.end()) return it->second;
+    if (rows) {
+        const int wn = nk >= 64 ? 2 : 1;
+        const int wm = g >= 8192 ? 4 : 2;
+        return TileCfg{wm, wn};
+    }
+    const int wm = nk >= 128 ? 4 : (nk >= 48 ? 2 : 1);
+    const int wn = B >= 128 ? 4 : (B >= 48 ? 2 : 1);
+    return TileCfg{wm, wn};
+}
+
+struct ProfScope {
+    Profiler& p; const char* name; hipStream_t s;
+    ProfScope(Profiler& p_, const char* n, hipStream_t s_) : p(p_), name(n), s(s_) { if (p.enabled) p.begin(name, s); }
+    ~ProfScope() { if (p.enabled) p.end(name, s); }
+};
+
+const void* fac_base(const cola_op_s* op, int prec) {
+    switch (prec) {
+        case COLA_PREC_FP64: return op->fac64;
+        case COLA_PREC_FP32: return op->fac32;
+        default: return op->facbf;
+    }
+}
+
+// Enqueue the passes of one MVM of system `s` on nrhs packed vectors `X`.
+// The last pass (mode 1) applies epilogue `epi`; PassArgs fields for the
+// epilogue and gating are taken from `tmpl`.
+int32_t enqueue_mvm(cola_op_s* op, const SysInfo& s, int prec, int nrhs, const void* X, const void* Rpnew,
+                    void* Yout, const PassArgs& tmpl, hipStream_t st) {
+    const size_t esz = (prec == COLA_PREC_FP64) ? sizeof(double) : sizeof(float);
+    const int64_t n = s.n;
+    const int64_t tstride = (int64_t)nrhs * n;         // between per-term intermediates
+    const void* fac = fac_base(op, prec);
+    const int64_t k_plane = op->fac_elems;
+    const void* diag = nullptr;
+    if (s.diag_off >= 0)
+        diag = (prec == COLA_PREC_FP64) ? (const void*)(op->diag64 + s.diag_off)
+                                        : (const void*)(op->diag32 + s.diag_off);
+    const void* in = X;
+    int64_t in_tstride = 0;
+    int buf = 0;
+    for (int k = s.Fv - 1; k >= 0; --k) {
+        PassArgs a = tmpl;
+        const int64_t nk = s.dims[k];
+        int64_t lead = 1, trail = 1;
+        for (int m = 0; m < k; ++m) lead *= s.dims[m];
+        for (int m = k + 1; m < s.Fv; ++m) trail *= s.dims[m];
+        a.nk = (int32_t)nk;
+        a.K = (const char*)fac + (size_t)s.fac_off[k] * (prec == COLA_PREC_FP64 ? 8 : (prec == COLA_PREC_FP32 ? 4 : 2));
+        a.k_tstride = nk * nk;
+        a.k_plane = k_plane;
+        a.X = in;
+        a.x_tstride = in_tstride;
+        a.pnew = (k == s.Fv - 1) && Rpnew != nullptr;
+        a.R = Rpnew;
+        const bool rows = (k == s.Fv - 1);
+        if (rows) {
+            a.G = (int64_t)nrhs * lead;
+            a.B = 1;
+            a.a_per_rhs = lead;
+        } else {
+            a.G = (int64_t)nrhs * lead;
+            a.B = trail;
+            a.a_per_rhs = lead;
+        }
+        const char* kname;
+        if (k == 0) {
+            a.nsum = s.J;
+            a.nout = 1;
+            a.Y = Yout;
+            a.y_tstride = 0;
+            a.dvec = diag;
+            a.sigma2 = s.sigma2;
+            kname = "contract_last";
+        } else {
+            a.nsum = 1;
+            a.nout = s.J;
+            a.Y = op->ws.inter[buf];
+            a.y_tstride = tstride;
+            a.epi = EPI_STORE;
+            kname = rows ? "contract_rows" : "contract_mid";
+        }
+        TileCfg cfg = tile_for(op, prec, rows, nk, a.B, a.a_per_rhs);
+        {
+            ProfScope ps(op->prof, kname, st);
+            HIP_TRY(launch_contract(prec, rows, a, cfg, st));
+        }
+        in = a.Y;
+        in_tstride = tstride;
+        buf ^= 1;
+        (void)esz;
+    }
+    return COLA_OK;
+}
+
+PassArgs base_args(cola_op_s* op) {
+    PassArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.partials = op->ws.partials;
+    a.part_stride = (int32_t)op->ws.part_stride;
+    a.counters = op->ws.counters;
+    a.cnt = op->ws.cnt;
+    return a;
+}
+
+int32_t poll_flag(cola_op_s* op, const int32_t* dev, hipStream_t st, int32_t* out) {
+    HIP_TRY(hipMemcpyAsync(op->ws.host_flag, dev, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    *out = *(volatile int32_t*)op->ws.host_flag;
+    return COLA_OK;
+}
+
+// CG iterations on prepared state: x, r, p, q are the working vectors.
+template <typename T>
+int32_t run_cg(cola_op_s* op, const SysInfo& s, int prec, int nrhs, T* x, T* r, T* p, T* q, int max_iters,
+               int check_every, hipStream_t st) {
+    Workspace& w = op->ws;
+    for (int it = 0; it < max_iters; ++it) {
+        if (check_every > 0 && it > 0 && it % check_every == 0) {
+            int32_t active = 0;
+            int32_t rc = poll_flag(op, &w.cnt->num_active, st, &active);
+            if (rc != COLA_OK) return rc;
+            if (active <= 0) break;
+        }
+        PassArgs a = base_args(op);
+        a.cg = w.cg;
+        a.epi = EPI_CG;
+        a.Ep = p;
+        a.Er = r;
+        a.Epout = p;
+        int32_t rc = enqueue_mvm(op, s, prec, nrhs, p, r, q, a, st);
+        if (rc != COLA_OK) return rc;
+        ProfScope ps(op->prof, "update", st);
+        HIP_TRY(cg_update<T>(x, r, p, q, s.n, nrhs, w.cg, w.partials, (int)w.part_stride, w.counters, w.cnt, st));
+    }
+    return COLA_OK;
+}
+
+int32_t solve_system(cola_op_s* op, const SysInfo& s, const double* B, double* X, int nrhs,
+                     const cola_solve_opts* o, cola_solve_info* info, hipStream_t st) {
+    Workspace& w = op->ws;
+    const int64_t n = s.n;
+    const int ps = (int)w.part_stride;
+    if (o->prec == COLA_PREC_FP64) {
+        HIP_TRY(fill_i32(&w.cnt->num_active, 0, 1, st));
+        double* r = (double*)w.vr;
+        double* p = (double*)w.vp;
+        double* q = (double*)w.vq;
+        HIP_TRY(cg_prepare<double>(B, r, X, p, n, nrhs, nullptr, w.cg, o->tol, o->max_iters, w.partials, ps,
+                                   w.counters, w.cnt, st));
+        int32_t rc = run_cg<double>(op, s, COLA_PREC_FP64, nrhs, X, r, p, q, o->max_iters, o->check_every, st);
+        if (rc != COLA_OK) return rc;
+        if (info) HIP_TRY(write_info(info, nullptr, w.cg, nrhs, st));
+        return COLA_OK;
+    }
+    // iterative refinement: FP64 residual, working-precision inner CG
+    HIP_TRY(fill_i32(&w.cnt->num_outer_active, 0, 1, st));
+    HIP_TRY(outer_init(B, X, n, nrhs, w.outer, o->tol, o->max_sweeps, w.partials, ps, w.counters, w.cnt, st));
+    float* xl = (float*)w.vx;
+    float* rl = (float*)w.vr;
+    float* pl = (float*)w.vp;
+    float* ql = (float*)w.vq;
+    for (int sweep = 0; sweep <= o->max_sweeps; ++sweep) {
+        PassArgs a = base_args(op);
+        a.outer = w.outer;
+        a.epi = EPI_RESID;
+        a.Ep = X;
+        a.Er = B;
+        int32_t rc = enqueue_mvm(op, s, COLA_PREC_FP64, nrhs, X, nullptr, w.r64, a, st);
+        if (rc != COLA_OK) return rc;
+        if (sweep == o->max_sweeps) break;
+        if (o->check_every > 0) {
+            int32_t active = 0;
+            rc = poll_flag(op, &w.cnt->num_outer_active, st, &active);
+            if (rc != COLA_OK) return rc;
+            if (active <= 0) break;
+        }
+        HIP_TRY(fill_i32(&w.cnt->num_active, 0, 1, st));
+        HIP_TRY(cg_prepare<float>(w.r64, rl, xl, pl, n, nrhs, w.outer, w.cg, o->inner_tol, o->max_iters,
+                                  w.partials, ps, w.counters, w.cnt, st));
+        rc = run_cg<float>(op, s, op->prec, nrhs, xl, rl, pl, ql, o->max_iters, o->check_every, st);
+        if (rc != COLA_OK) return rc;
+        HIP_TRY(refine_accumulate<float>(X, xl, n, nrhs, w.outer, st));
+        HIP_TRY(outer_bookkeep(w.outer, w.cg, nrhs, w.cnt, st));
+    }
+    if (info) HIP_TRY(write_info(info, w.outer, nullptr, nrhs, st));
+    return COLA_OK;
+}
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+int32_t check_opts(const cola_op_s* op, const cola_solve_opts* o) {
+    if (!o) return COLA_ERR_INVALID_ARG;
+    if (!finite_pos(o->tol) || o->max_iters < 1 || o->check_every < 0) return COLA_ERR_INVALID_ARG;
+    if (o->prec != COLA_PREC_FP64) {
+        if (o->prec != op->prec) return COLA_ERR_INVALID_ARG;
+        if (!finite_pos(o->inner_tol) || o->max_sweeps < 1) return COLA_ERR_INVALID_ARG;
+    }
+    return COLA_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+extern "C" {
+
+const char* cola_status_string(int32_t status) {
+    switch (status) {
+        case COLA_OK: return "ok";
+        case COLA_NOT_CONVERGED: return "not converged: iteration or sweep limit reached";
+        case COLA_STAGNATED: return "stagnated: refinement stopped reducing the residual";
+        case COLA_ERR_INVALID_ARG: return "invalid argument";
+        case COLA_ERR_NOT_SPD: return "operator not positive definite (CG breakdown p^T A p <= 0)";
+        case COLA_ERR_NONFINITE: return "non-finite value (NaN/Inf) in the data or the iteration";
+        case COLA_ERR_OOM: return "device memory allocation failed";
+        case COLA_ERR_HIP: return "HIP runtime error";
+        case COLA_ERR_UNSUPPORTED: return "unsupported configuration";
+        default: return "unknown status";
+    }
+}
+
+int32_t cola_op_create(const cola_system_desc* systems, int32_t nsys, int32_t prec, void* stream,
+                       cola_op_t* out) {
+    if (!out) return COLA_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (!systems || nsys < 1) return COLA_ERR_INVALID_ARG;
+    if (prec < COLA_PREC_FP64 || prec > COLA_PREC_BF16X3) return COLA_ERR_INVALID_ARG;
+    cola_op_s* op = new (std::nothrow) cola_op_s();
+    if (!op) return COLA_ERR_OOM;
+    op->prec = prec;
+    (void)hipGetDevice(&op->device);
+    hipStream_t st = S(stream);
+
+    int64_t fac = 0, dg = 0, voff = 0, goff = 0;
+    for (int i = 0; i < nsys; ++i) {
+        const cola_system_desc& d = systems[i];
+        if (d.nterms < 1 || d.nfactors < 1 || d.nfactors > 3 || !d.factors || !std::isfinite(d.sigma2) ||
+            d.sigma2 < 0.0) {
+            delete op;
+            return COLA_ERR_INVALID_ARG;
+        }
+        SysInfo s;
+        s.J = d.nterms;
+        s.F = d.nfactors;
+        s.Fv = std::max(2, s.F);
+        int64_t n = 1;
+        for (int k = 0; k < s.F; ++k) {
+            if (d.dims[k] < 1 || d.dims[k] > (1 << 20)) {
+                delete op;
+                return COLA_ERR_INVALID_ARG;
+            }
+            n *= d.dims[k];
+        }
+        if (n > ((int64_t)1 << 36)) {
+            delete op;
+            return COLA_ERR_INVALID_ARG;
+        }
+        if (s.F == 1) {
+            s.dims[0] = 1;
+            s.dims[1] = d.dims[0];
+        } else {
+            for (int k = 0; k < s.F; ++k) s.dims[k] = d.dims[k];
+        }
+        for (int j = 0; j < s.J * s.F; ++j)
+            if (!d.factors[j]) {
+                delete op;
+                return COLA_ERR_INVALID_ARG;
+            }
+        s.n = n;
+        for (int k = 0; k < s.Fv; ++k) {
+            s.fac_off[k] = fac;
+            fac += (int64_t)s.J * s.dims[k] * s.dims[k];
+        }
+        if (d.diag) {
+            s.diag_off = dg;
+            dg += n;
+        }
+        s.sigma2 = d.sigma2;
+        s.vec_off = voff;
+        voff += n;
+        s.grad_off = goff;
+        goff += (int64_t)s.J * s.F;
+        op->sys.push_back(s);
+        op->nmax = std::max(op->nmax, n);
+        op->Jmax = std::max(op->Jmax, s.J);
+    }
+    op->n_total = voff;
+    op->fac_elems = fac;
+    op->diag_elems = dg;
+
+    int32_t rc = alloc_bytes((void**)&op->fac64, sizeof(double) * fac);
+    if (rc == COLA_OK && dg > 0) rc = alloc_bytes((void**)&op->diag64, sizeof(double) * dg);
+    if (rc != COLA_OK) {
+        cola_op_destroy(op);
+        return rc;
+    }
+    // copy factors into the packed FP64 master (mode-major, then term)
+    for (int i = 0; i < nsys; ++i) {
+        const cola_system_desc& d = systems[i];
+        const SysInfo& s = op->sys[i];
+        for (int k = 0; k < s.Fv; ++k) {
+            const int64_t nk = s.dims[k];
+            for (int j = 0; j < s.J; ++j) {
+                double* dst = op->fac64 + s.fac_off[k] + (int64_t)j * nk * nk;
+                hipError_t e;
+                if (s.F == 1 && k == 0) {
+                    e = fill_f64(dst, 1.0, 1, st);               // the implicit [1] factor
+                } else {
+                    const int kk = (s.F == 1) ? 0 : k;
+                    e = hipMemcpyAsync(dst, d.factors[j * s.F + kk], sizeof(double) * nk * nk,
+                                       hipMemcpyDeviceToDevice, st);
+                }
+                if (e != hipSuccess) {
+                    cola_op_destroy(op);
+                    return COLA_ERR_HIP;
+                }
+            }
+        }
+        if (d.diag && hipMemcpyAsync(op->diag64 + s.diag_off, d.diag, sizeof(double) * s.n,
+                                     hipMemcpyDeviceToDevice, st) != hipSuccess) {
+            cola_op_destroy(op);
+            return COLA_ERR_HIP;
+        }
+    }
+    // working copies
+    if (prec != COLA_PREC_FP64) {
+        rc = alloc_bytes((void**)&op->fac32, sizeof(float) * fac);
+        if (rc == COLA_OK && dg > 0) rc = alloc_bytes((void**)&op->diag32, sizeof(float) * dg);
+        if (rc == COLA_OK && (prec == COLA_PREC_BF16 || prec == COLA_PREC_BF16X3)) {
+            op->nsplit = (prec == COLA_PREC_BF16) ? 1 : 3;
+            rc = alloc_bytes((void**)&op->facbf, sizeof(__bf16) * fac * op->nsplit);
+        }
+        if (rc != COLA_OK) {
+            cola_op_destroy(op);
+            return rc;
+        }
+        if (convert_f64_f32(op->fac64, op->fac32, fac, st) != hipSuccess ||
+            (dg > 0 && convert_f64_f32(op->diag64, op->diag32, dg, st) != hipSuccess) ||
+            (op->facbf && convert_f64_bf16_split(op->fac64, op->facbf, fac, op->nsplit, fac, st) != hipSuccess)) {
+            cola_op_destroy(op);
+            return COLA_ERR_HIP;
+        }
+    }
+    *out = op;
+    return COLA_OK;
+}
+
+int32_t cola_op_destroy(cola_op_t op) {
+    if (!op) return COLA_OK;
+    (void)hipDeviceSynchronize();
+    free_ws(op->ws);
+    void* ptrs[] = {op->fac64, op->fac32, op->facbf, op->diag64, op->diag32, op->grad_buf};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    delete op;
+    return COLA_OK;
+}
+
+int32_t cola_op_size(cola_op_t op, int64_t* n_total, int32_t* nsys) {
+    if (!op) return COLA_ERR_INVALID_ARG;
+    if (n_total) *n_total = op->n_total;
+    if (nsys) *nsys = (int32_t)op->sys.size();
+    return COLA_OK;
+}
+
+int32_t cola_kron_matvec(cola_op_t op, const void* X, void* Y, int32_t nrhs, int32_t dtype, int32_t prec,
+                         void* stream) {
+    if (!op || !X || !Y || nrhs < 1) return COLA_ERR_INVALID_ARG;
+    if (prec == COLA_PREC_FP64) {
+        if (dtype != COLA_F64) return COLA_ERR_INVALID_ARG;
+    } else {
+        if (prec != op->prec || dtype != COLA_F32) return COLA_ERR_INVALID_ARG;
+    }
+    hipStream_t st = S(stream);
+    int32_t rc = ensure_ws(op, nrhs, st);
+    if (rc != COLA_OK) return rc;
+    const size_t esz = (dtype == COLA_F64) ? 8 : 4;
+    for (const SysInfo& s : op->sys) {
+        const char* xs = (const char*)X + esz * (size_t)nrhs * s.vec_off;
+        char* ys = (char*)Y + esz * (size_t)nrhs * s.vec_off;
+        PassArgs a = base_args(op);
+        a.epi = EPI_MATVEC;
+        a.Ep = xs;
+        rc = enqueue_mvm(op, s, prec, nrhs, xs, nullptr, ys, a, st);
+        if (rc != COLA_OK) return rc;
+    }
+    return COLA_OK;
+}
+
+int32_t cola_cg_solve(cola_op_t op, const double* B, double* X, int32_t nrhs, const cola_solve_opts* opts,
+                      cola_solve_info* info, void* stream) {
+    if (!op || !B || !X || nrhs < 1) return COLA_ERR_INVALID_ARG;
+    int32_t rc = check_opts(op, opts);
+    if (rc != COLA_OK) return rc;
+    hipStream_t st = S(stream);
+    rc = ensure_ws(op, nrhs, st);
+    if (rc != COLA_OK) return rc;
+    for (size_t i = 0; i < op->sys.size(); ++i) {
+        const SysInfo& s = op->sys[i];
+        const size_t off = (size_t)nrhs * s.vec_off;
+        rc = solve_system(op, s, B + off, X + off, nrhs, opts, info ? info + i * nrhs : nullptr, st);
+        if (rc != COLA_OK) return rc;
+    }
+    return COLA_OK;
+}
+
+int32_t cola_cg_solve_backward(cola_op_t op, const double* X, const double* G, int32_t nrhs,
+                               const cola_solve_opts* opts, double* Lambda, void* const* dfactors,
+                               void* const* ddiag, double* dsigma2, cola_solve_info* info, void* stream) {
+    if (!op || !X || !G || !Lambda || nrhs < 1) return COLA_ERR_INVALID_ARG;
+    int32_t rc = cola_cg_solve(op, G, Lambda, nrhs, opts, info, stream);
+    if (rc != COLA_OK) return rc;
+    hipStream_t st = S(stream);
+    for (size_t i = 0; i < op->sys.size(); ++i) {
+        const SysInfo& s = op->sys[i];
+        const size_t off = (size_t)nrhs * s.vec_off;
+        rc = grad_system(op, s, X + off, Lambda + off, nrhs, dfactors ? dfactors + s.grad_off : nullptr,
+                         ddiag ? ddiag[i] : nullptr, dsigma2 ? dsigma2 + i : nullptr, st);
+        if (rc != COLA_OK) return rc;
+    }
+    return COLA_OK;
+}
+
+int32_t cola_autotune(cola_op_t op, int32_t nrhs, void* stream) {
+    if (!op || nrhs < 1) return COLA_ERR_INVALID_ARG;
+    return autotune_op(op, nrhs, S(stream));
+}
+
+int32_t cola_profile_enable(cola_op_t op, int32_t enable) {
+    if (!op) return COLA_ERR_INVALID_ARG;
+    (void)hipDeviceSynchronize();
+    op->prof.clear();
+    op->prof.enabled = enable != 0;
+    return COLA_OK;
+}
+
+int32_t cola_profile_read(cola_op_t op, const char* kernel, double* total_ms, int64_t* launches) {
+    if (!op || !kernel || !total_ms || !launches) return COLA_ERR_INVALID_ARG;
+    if (hipDeviceSynchronize() != hipSuccess) return COLA_ERR_HIP;
+    op->prof.read(kernel, total_ms, launches);
+    return COLA_OK;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+namespace cola {
+
+int32_t ensure_workspace(cola_op_s* op, int nrhs, hipStream_t st) { return ensure_ws(op, nrhs, st); }
+
+hipEvent_t Profiler::get() {
+    if (!pool_.empty()) {
+        hipEvent_t e = pool_.back();
+        pool_.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+}
+
+void Profiler::begin(const char* name, hipStream_t s) {
+    hipEvent_t e = get();
+    (void)hipEventRecord(e, s);
+    pending_[name] = e;
+}
+
+void Profiler::end(const char* name, hipStream_t s) {
+    auto it = pending_.find(name);
+    if (it == pending_.end()) return;
+    hipEvent_t e = get();
+    (void)hipEventRecord(e, s);
+    open_[name].push_back({it->second, e});
+    pending_.erase(it);
+}
+
+void Profiler::read(const std::string& name, double* ms, int64_t* launches) {
+    *ms = 0.0;
+    *launches = 0;
+    auto it = open_.find(name);
+    if (it == open_.end()) return;
+    for (auto& pr : it->second) {
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, pr.first, pr.second) == hipSuccess) {
+            *ms += t;
+            *launches += 1;
+        }
+    }
+}
+
+void Profiler::clear() {
+    for (auto& kv : open_)
+        for (auto& pr : kv.second) {
+            pool_.push_back(pr.first);
+            pool_.push_back(pr.second);
+        }
+    open_.clear();
+    for (auto& kv : pending_) pool_.push_back(kv.second);
+    pending_.clear();
+}
+
+Profiler::~Profiler() {
+    clear();
+    for (hipEvent_t e : pool_) (void)hipEventDestroy(e);
+}
+
+}  // namespace cola

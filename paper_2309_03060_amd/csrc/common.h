@@ -1,0 +1,122 @@
+// Internal definitions shared by the HIP sources of libcola (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+#include <stdint.h>
+
+#include "../../include/cola.h"
+
+namespace cola {
+
+constexpr int kThreads = 256;          // every kernel runs 4 waves of 64 lanes
+
+typedef float  floatx4  __attribute__((ext_vector_type(4)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8   __attribute__((ext_vector_type(8)));
+
+// ---------------------------------------------------------------------------
+// Per right-hand-side CG state (device memory, one per RHS of the current
+// system).  Updated only by the last block of a reduction.
+struct CgState {
+    double rho;        // r.r of the current residual
+    double alpha;      // rho / (p.Ap) of the current iteration
+    double beta;       // rho_new / rho_old; 0 before the first direction
+    double tol2;       // (tol * ||b||)^2 - stop when rho <= tol2
+    double bnorm2;     // ||b||^2 of this solve's right-hand side
+    int32_t active;    // 1 while iterating
+    int32_t iters;
+    int32_t status;    // COLA_* numerical status of this solve
+    int32_t max_iters;
+};
+
+// Refinement (outer) state, one per RHS.
+struct OuterState {
+    double bnorm2;     // ||b||^2 of the caller's right-hand side (FP64)
+    double rnorm;      // ||b - A x|| of the latest FP64 residual
+    double prev_rnorm; // previous sweep's ||r|| (inf before the first)
+    double relres;     // rnorm / ||b||
+    double tol;        // target relative residual
+    int32_t active;
+    int32_t slow;      // consecutive sweeps that failed to halve ||r||
+    int32_t sweeps;
+    int32_t status;
+    int32_t iters;     // inner iterations summed over sweeps
+    int32_t max_sweeps;
+};
+
+// Counters shared by all RHS of a solve (device memory).
+struct SolveCounters {
+    int32_t num_active;       // RHS still iterating in the current inner solve
+    int32_t num_outer_active; // RHS still refining
+};
+
+// ---------------------------------------------------------------------------
+// Wave / block reductions (fixed order, hence deterministic).
+__device__ inline double wave_sum(double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Sum over the 256 threads of a block; the result is valid in every thread.
+__device__ inline double block_sum(double v, double* smem /* >= 4 doubles */) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) smem[wave] = v;
+    __syncthreads();
+    double s = smem[0] + smem[1] + smem[2] + smem[3];
+    __syncthreads();
+    return s;
+}
+
+// Coherent (L1-bypassing) accesses for data exchanged between blocks of one launch.
+__device__ inline double load_coherent(const double* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void store_coherent(double* p, double v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Last-block-done reduction: every block of a group publishes one partial;
+// the block that arrives last sums the group's partials in index order and
+// returns true (in all its threads) with the total in *total.  The counter
+// is reset by that block so the next launch starts from zero.  No block ever
+// waits for another, so the pattern cannot hang.
+__device__ inline bool last_block_reduce(double partial, double* partials, uint32_t* counter,
+                                         int nblocks, int myblock, double* total,
+                                         double* smem) {
+    __shared__ int s_last;
+    if (threadIdx.x == 0) {
+        store_coherent(&partials[myblock], partial);
+        __atomic_thread_fence(__ATOMIC_RELEASE);  // publish before counting (device scope)
+        uint32_t prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+        s_last = (prev == (uint32_t)(nblocks - 1));
+    }
+    __syncthreads();
+    if (!s_last) return false;
+    __atomic_thread_fence(__ATOMIC_ACQUIRE);
+    double s = 0.0;
+    for (int i = threadIdx.x; i < nblocks; i += blockDim.x) s += load_coherent(&partials[i]);
+    s = block_sum(s, smem);
+    if (threadIdx.x == 0)
+        __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    *total = s;
+    return true;
+}
+
+// Row (within a 16x16 tile) of accumulator element v held by `lane`.  The
+// column is always lane % 16.  FP32/BF16 16x16 MFMAs give each lane four
+// consecutive rows; the FP64 16x16x4 MFMA interleaves them by 4.
+__device__ inline int acc_row(float, int lane, int v)  { return 4 * (lane >> 4) + v; }
+__device__ inline int acc_row(double, int lane, int v) { return 4 * v + (lane >> 4); }
+
+__device__ inline bool finite_d(double v) { return __builtin_isfinite(v); }
+
+// p_new = r + beta * p_old, evaluated identically wherever it is needed so
+// that every kernel of an iteration sees the same rounded direction.
+__device__ inline float  pnew_of(float r, float p, double beta)   { return __builtin_fmaf((float)beta, p, r); }
+__device__ inline double pnew_of(double r, double p, double beta) { return __builtin_fma(beta, p, r); }
+
+}  // namespace cola

@@ -1,0 +1,370 @@
+// Mode contraction pass of the Kronecker MVM on gfx950 matrix cores.
+//
+// A Kronecker term applied to x (row-major vec) multiplies every tensor mode
+// of X = x.reshape(n1, .., nF) by its factor; the MVM cost of Table 2
+// (tau_A N_B + N_A tau_B) is exactly the sum of these per-mode products.
+// Each pass here is one such mode product, written as a batched GEMM with a
+// small inner dimension (the mode size) and staged through LDS:
+//
+//   ROWS  (last mode):  Y[g, i]    = sum_l X[g, l] K[i, l]     (g: all leading indices)
+//   COLS  (other modes): Y[g, i, b] = sum_l K[i, l] X[g, l, b]  (b: trailing indices)
+//
+// Operands are staged in LDS as [row][k] tiles (k contiguous) and fed to
+// 16x16 MFMA tiles; each of the 4 waves owns a (16*WM) x (16*WN) sub-tile.
+// Precision policies: FP64 (v_mfma_f64_16x16x4f64), FP32 (v_mfma_f32_16x16x4f32),
+// BF16 (v_mfma_f32_16x16x32_bf16, FP32 accumulation) and BF16x3 (each operand
+// split into three bf16 parts; the six leading cross products are summed).
+//
+// The last pass of an MVM carries the fused epilogues of the CG iteration
+// (the diagonal term of the Sum, the search-direction update and the partial
+// dot product p.Ap) or of the FP64 refinement residual r = b - A x.
+#include "contract.h"
+
+namespace cola {
+
+// ----------------------------------------------------------------------------
+// precision policies
+struct PolF64 {
+    using V = double; using Fac = double; using L = double; using Acc = doublex4;
+    static constexpr int KT = 16, KSTEP = 4, NS = 1, KP = KT + 2;
+};
+struct PolF32 {
+    using V = float; using Fac = float; using L = float; using Acc = floatx4;
+    static constexpr int KT = 32, KSTEP = 4, NS = 1, KP = KT + 4;
+};
+struct PolBF16 {
+    using V = float; using Fac = __bf16; using L = __bf16; using Acc = floatx4;
+    static constexpr int KT = 32, KSTEP = 32, NS = 1, KP = KT + 8;
+};
+struct PolBF16X3 {
+    using V = float; using Fac = __bf16; using L = __bf16; using Acc = floatx4;
+    static constexpr int KT = 32, KSTEP = 32, NS = 3, KP = KT + 8;
+};
+
+template <class P> struct IsBf { static constexpr bool value = false; };
+template <> struct IsBf<PolBF16> { static constexpr bool value = true; };
+template <> struct IsBf<PolBF16X3> { static constexpr bool value = true; };
+
+__device__ inline floatx4 mma(float a, float b, floatx4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ inline doublex4 mma(double a, double b, doublex4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ inline floatx4 mma(bf16x8 a, bf16x8 b, floatx4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// Split a working-precision value into the policy's LDS parts.
+template <class P>
+__device__ inline void split_value(typename P::V v, typename P::L* out) {
+    if constexpr (!IsBf<P>::value) {
+        out[0] = v;
+    } else {
+        __bf16 h = (__bf16)v;                  // round to nearest even
+        out[0] = h;
+        if constexpr (P::NS == 3) {
+            float r1 = v - (float)h;
+            __bf16 m = (__bf16)r1;
+            float r2 = r1 - (float)m;
+            out[1] = m;
+            out[2] = (__bf16)r2;
+        }
+    }
+}
+
+__device__ inline bool gate_of(const PassArgs& a, int64_t rhs) {
+    if (a.cg) return a.cg[rhs].active != 0;
+    if (a.outer) return a.outer[rhs].active != 0;
+    return true;
+}
+
+template <class P, int WM, int WN, bool ROWS>
+__global__ __launch_bounds__(kThreads) void k_contract(PassArgs a) {
+    using V = typename P::V; using Fac = typename P::Fac; using L = typename P::L;
+    using Acc = typename P::Acc;
+    constexpr int MT = 32 * WM, NT = 32 * WN, KT = P::KT, KP = P::KP, NS = P::NS;
+    __shared__ __attribute__((aligned(16))) L As[NS][MT * KP];
+    __shared__ __attribute__((aligned(16))) L Bs[NS][NT * KP];
+    __shared__ double red[4];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int nk = a.nk;
+    const int64_t k_plane = a.k_plane;
+
+    int64_t g = 0, m0, n0, nBt = 1;
+    int nMt = 1, tout;
+    if constexpr (ROWS) {
+        const int nNt = (nk + NT - 1) / NT;
+        m0 = (int64_t)blockIdx.x * MT;
+        n0 = (int64_t)(blockIdx.y % nNt) * NT;
+        tout = blockIdx.y / nNt;
+        if (a.cg || a.outer) {
+            const int64_t last = (m0 + MT < a.G ? m0 + MT : a.G) - 1;
+            bool any = false;
+            for (int64_t r = m0 / a.a_per_rhs; r <= last / a.a_per_rhs; ++r) any |= gate_of(a, r);
+            if (!any) return;
+        }
+    } else {
+        nBt = (a.B + NT - 1) / NT;
+        g = blockIdx.x / nBt;
+        n0 = (int64_t)(blockIdx.x % nBt) * NT;
+        nMt = (nk + MT - 1) / MT;
+        m0 = (int64_t)(blockIdx.y % nMt) * MT;
+        tout = blockIdx.y / nMt;
+        if (!gate_of(a, g / a.a_per_rhs)) return;
+    }
+
+    Acc acc[WM][WN];
+#pragma unroll
+    for (int i = 0; i < WM; ++i)
+#pragma unroll
+        for (int j = 0; j < WN; ++j) acc[i][j] = Acc{0, 0, 0, 0};
+
+    // beta of the CG direction update for COLS (one batch per block)
+    double beta_blk = 0.0;
+    if (!ROWS && a.pnew) beta_blk = a.cg[g / a.a_per_rhs].beta;
+
+    for (int t = 0; t < a.nsum; ++t) {
+        const int tt = (a.nsum > 1) ? t : tout;
+        const Fac* Kp = (const Fac*)a.K + (int64_t)tt * a.k_tstride;
+        const V* Xp = (const V*)a.X + (int64_t)tt * a.x_tstride;
+        const V* Rp = (const V*)a.R + (int64_t)tt * a.x_tstride;
+        for (int k0 = 0; k0 < nk; k0 += KT) {
+            // ---- stage A tile (MT x KT) ----
+            for (int e = tid; e < MT * KT; e += kThreads) {
+                const int m = e / KT, k = e % KT;
+                const int64_t gm = m0 + m;
+                const int gk = k0 + k;
+                L parts[NS];
+                if constexpr (ROWS) {
+                    V v = 0;
+                    if (gm < a.G && gk < nk) {
+                        const int64_t idx = gm * nk + gk;
+                        v = Xp[idx];
+                        if (a.pnew) v = pnew_of(Rp[idx], v, a.cg[gm / a.a_per_rhs].beta);
+                    }
+                    split_value<P>(v, parts);
+                } else {
+                    const bool in = (gm < nk && gk < nk);
+#pragma unroll
+                    for (int s = 0; s < NS; ++s)
+                        parts[s] = in ? (L)Kp[s * k_plane + gm * nk + gk] : (L)0.0f;
+                }
+#pragma unroll
+                for (int s = 0; s < NS; ++s) As[s][m * KP + k] = parts[s];
+            }
+            // ---- stage B tile (NT x KT) ----
+            for (int e = tid; e < NT * KT; e += kThreads) {
+                L parts[NS];
+                int n, k;
+                if constexpr (ROWS) {
+                    n = e / KT; k = e % KT;
+                    const int64_t gn = n0 + n;
+                    const int gk = k0 + k;
+                    const bool in = (gn < nk && gk < nk);
+#pragma unroll
+                    for (int s = 0; s < NS; ++s)
+                        parts[s] = in ? (L)Kp[s * k_plane + gn * nk + gk] : (L)0.0f;
+                } else {
+                    n = e % NT; k = e / NT;
+                    const int64_t gn = n0 + n;
+                    const int gk = k0 + k;
+                    V v = 0;
+                    if (gn < a.B && gk < nk) {
+                        const int64_t idx = (g * nk + gk) * a.B + gn;
+                        v = Xp[idx];
+                        if (a.pnew) v = pnew_of(Rp[idx], v, beta_blk);
+                    }
+                    split_value<P>(v, parts);
+                }
+#pragma unroll
+                for (int s = 0; s < NS; ++s) Bs[s][n * KP + k] = parts[s];
+            }
+            __syncthreads();
+            // ---- MFMA over the staged K slice ----
+#pragma unroll
+            for (int kk = 0; kk < KT; kk += P::KSTEP) {
+                if constexpr (!IsBf<P>::value) {
+                    L av[WM], bv[WN];
+#pragma unroll
+                    for (int i = 0; i < WM; ++i)
+                        av[i] = As[0][(wm * WM * 16 + i * 16 + (lane & 15)) * KP + kk + (lane >> 4)];
+#pragma unroll
+                    for (int j = 0; j < WN; ++j)
+                        bv[j] = Bs[0][(wn * WN * 16 + j * 16 + (lane & 15)) * KP + kk + (lane >> 4)];
+#pragma unroll
+                    for (int i = 0; i < WM; ++i)
+#pragma unroll
+                        for (int j = 0; j < WN; ++j) acc[i][j] = mma(av[i], bv[j], acc[i][j]);
+                } else {
+                    bf16x8 av[NS][WM], bv[NS][WN];
+#pragma unroll
+                    for (int s = 0; s < NS; ++s) {
+#pragma unroll
+                        for (int i = 0; i < WM; ++i)
+                            av[s][i] = *(const bf16x8*)&As[s][(wm * WM * 16 + i * 16 + (lane & 15)) * KP + kk + 8 * (lane >> 4)];
+#pragma unroll
+                        for (int j = 0; j < WN; ++j)
+                            bv[s][j] = *(const bf16x8*)&Bs[s][(wn * WN * 16 + j * 16 + (lane & 15)) * KP + kk + 8 * (lane >> 4)];
+                    }
+#pragma unroll
+                    for (int i = 0; i < WM; ++i)
+#pragma unroll
+                        for (int j = 0; j < WN; ++j) {
+                            if constexpr (NS == 1) {
+                                acc[i][j] = mma(av[0][i], bv[0][j], acc[i][j]);
+                            } else {
+                                // smallest products first: lo*hi, hi*lo, mid*mid, mid*hi, hi*mid, hi*hi
+                                acc[i][j] = mma(av[2][i], bv[0][j], acc[i][j]);
+                                acc[i][j] = mma(av[0][i], bv[2][j], acc[i][j]);
+                                acc[i][j] = mma(av[1][i], bv[1][j], acc[i][j]);
+                                acc[i][j] = mma(av[1][i], bv[0][j], acc[i][j]);
+                                acc[i][j] = mma(av[0][i], bv[1][j], acc[i][j]);
+                                acc[i][j] = mma(av[0][i], bv[0][j], acc[i][j]);
+                            }
+                        }
+                }
+            }
+            __syncthreads();
+        }
+    }
+
+    // ---- epilogue ----
+    double dot = 0.0;
+    V* Y = (V*)a.Y + (int64_t)tout * a.y_tstride;
+    double beta_e = 0.0;
+    if (!ROWS && a.epi == EPI_CG) beta_e = a.cg[g].beta;
+#pragma unroll
+    for (int i = 0; i < WM; ++i)
+#pragma unroll
+        for (int j = 0; j < WN; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t m = m0 + wm * WM * 16 + i * 16 + acc_row(acc[i][j][v], lane, v);
+                const int64_t n = n0 + wn * WN * 16 + j * 16 + (lane & 15);
+                const V val = (V)acc[i][j][v];
+                if constexpr (ROWS) {
+                    if (m < a.G && n < nk) Y[m * nk + n] = val;
+                } else {
+                    if (m < nk && n < a.B) {
+                        const int64_t e = m * a.B + n;
+                        const int64_t idx = g * (int64_t)nk * a.B + e;
+                        if (a.epi == EPI_STORE) {
+                            Y[idx] = val;
+                        } else {
+                            V dg = (V)a.sigma2;
+                            if (a.dvec) dg += ((const V*)a.dvec)[e];
+                            if (a.epi == EPI_CG) {
+                                const V pn = pnew_of(((const V*)a.Er)[idx], ((const V*)a.Ep)[idx], beta_e);
+                                const V q = val + dg * pn;
+                                Y[idx] = q;
+                                ((V*)a.Epout)[idx] = pn;
+                                dot += (double)pn * (double)q;
+                            } else if (a.epi == EPI_RESID) {
+                                const V x = ((const V*)a.Ep)[idx];
+                                const V r = ((const V*)a.Er)[idx] - (val + dg * x);
+                                Y[idx] = r;
+                                dot += (double)r * (double)r;
+                            } else {  // EPI_MATVEC
+                                Y[idx] = val + dg * ((const V*)a.Ep)[idx];
+                            }
+                        }
+                    }
+                }
+            }
+
+    if constexpr (!ROWS) {
+        if (a.epi == EPI_CG || a.epi == EPI_RESID) {
+            const double s = block_sum(dot, red);
+            const int64_t nblk = nBt * nMt;
+            const int64_t myb = (blockIdx.x % nBt) + nBt * (blockIdx.y % nMt);
+            double tot;
+            if (last_block_reduce(s, a.partials + g * a.part_stride, a.counters + g, (int)nblk,
+                                  (int)myb, &tot, red) && tid == 0) {
+                if (a.epi == EPI_CG) {
+                    CgState& st = a.cg[g];
+                    if (!(tot > 0.0) || !finite_d(tot)) {
+                        st.status = finite_d(tot) ? COLA_ERR_NOT_SPD : COLA_ERR_NONFINITE;
+                        st.active = 0;
+                        atomicSub(&a.cnt->num_active, 1);
+                    } else {
+                        st.alpha = st.rho / tot;
+                    }
+                } else {
+                    OuterState& o = a.outer[g];
+                    const double rn = sqrt(tot);
+                    const double bn = sqrt(o.bnorm2);
+                    o.rnorm = rn;
+                    o.relres = bn > 0.0 ? rn / bn : rn;
+                    int status = -100;   // still refining
+                    if (!finite_d(rn)) status = COLA_ERR_NONFINITE;
+                    else if (o.relres <= o.tol) status = COLA_OK;
+                    else {
+                        o.slow = (rn > 0.5 * o.prev_rnorm) ? o.slow + 1 : 0;
+                        if (o.slow >= 2) status = COLA_STAGNATED;
+                        else if (o.sweeps >= o.max_sweeps) status = COLA_NOT_CONVERGED;
+                    }
+                    o.prev_rnorm = rn;
+                    if (status != -100) {
+                        o.status = status;
+                        o.active = 0;
+                        atomicSub(&a.cnt->num_outer_active, 1);
+                    }
+                }
+            }
+        }
+    }
+}
+
+// ----------------------------------------------------------------------------
+template <class P, int WM, int WN>
+static hipError_t launch_t(bool rows, const PassArgs& a, hipStream_t s) {
+    constexpr int MT = 32 * WM, NT = 32 * WN;
+    dim3 grid;
+    if (rows) {
+        const int64_t nNt = (a.nk + NT - 1) / NT;
+        grid = dim3((unsigned)((a.G + MT - 1) / MT), (unsigned)(nNt * a.nout), 1);
+        hipLaunchKernelGGL((k_contract<P, WM, WN, true>), grid, dim3(kThreads), 0, s, a);
+    } else {
+        const int64_t nBt = (a.B + NT - 1) / NT;
+        const int64_t nMt = (a.nk + MT - 1) / MT;
+        grid = dim3((unsigned)(a.G * nBt), (unsigned)(nMt * a.nout), 1);
+        hipLaunchKernelGGL((k_contract<P, WM, WN, false>), grid, dim3(kThreads), 0, s, a);
+    }
+    return hipGetLastError();
+}
+
+template <class P>
+static hipError_t launch_p(bool rows, const PassArgs& a, TileCfg c, hipStream_t s) {
+    switch (c.wm * 8 + c.wn) {
+        case 9:  return launch_t<P, 1, 1>(rows, a, s);
+        case 10: return launch_t<P, 1, 2>(rows, a, s);
+        case 12: return launch_t<P, 1, 4>(rows, a, s);
+        case 17: return launch_t<P, 2, 1>(rows, a, s);
+        case 18: return launch_t<P, 2, 2>(rows, a, s);
+        case 20: return launch_t<P, 2, 4>(rows, a, s);
+        case 33: return launch_t<P, 4, 1>(rows, a, s);
+        case 34: return launch_t<P, 4, 2>(rows, a, s);
+        case 36: return launch_t<P, 4, 4>(rows, a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_contract(int prec, bool rows, const PassArgs& a, TileCfg cfg, hipStream_t s) {
+    switch (prec) {
+        case COLA_PREC_FP64:   return launch_p<PolF64>(rows, a, cfg, s);
+        case COLA_PREC_FP32:   return launch_p<PolF32>(rows, a, cfg, s);
+        case COLA_PREC_BF16:   return launch_p<PolBF16>(rows, a, cfg, s);
+        case COLA_PREC_BF16X3: return launch_p<PolBF16X3>(rows, a, cfg, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+int64_t contract_blocks_per_g(int /*prec*/, const PassArgs& a, TileCfg cfg) {
+    const int64_t MT = 32 * cfg.wm, NT = 32 * cfg.wn;
+    return ((a.B + NT - 1) / NT) * ((a.nk + MT - 1) / MT);
+}
+
+}  // namespace cola

@@ -1,0 +1,94 @@
+// Operator handle and workspace (host side of libcola).
+#pragma once
+#include <map>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "common.h"
+#include "contract.h"
+
+namespace cola {
+
+// One independent system, with the Kronecker structure made at least two
+// modes deep (a single dense factor K becomes [1] (x) K).
+struct SysInfo {
+    int J = 1;             // terms
+    int F = 2;             // factors as given (1..3)
+    int Fv = 2;            // modes used by the passes (max(F, 2))
+    int64_t dims[3] = {1, 1, 1};
+    int64_t n = 1;
+    int64_t fac_off[3] = {0, 0, 0};   // mode k: term t's factor at fac_off[k] + t*dims[k]^2
+    int64_t diag_off = -1;            // offset in the diagonal buffers, -1: none
+    double sigma2 = 0.0;
+    int64_t vec_off = 0;              // unknowns of all earlier systems
+    int64_t grad_off = 0;             // this system's first entry in a dfactors pointer list
+};
+
+struct Workspace {
+    int nrhs = 0;
+    int64_t part_stride = 0;
+    void* vx = nullptr; void* vr = nullptr; void* vp = nullptr; void* vq = nullptr;  // CG vectors (8 B / elem)
+    void* inter[2] = {nullptr, nullptr};                                             // MVM intermediates
+    double* r64 = nullptr;                                                            // FP64 residual
+    double* partials = nullptr;
+    uint32_t* counters = nullptr;
+    CgState* cg = nullptr;
+    OuterState* outer = nullptr;
+    SolveCounters* cnt = nullptr;
+    int32_t* host_flag = nullptr;     // pinned
+};
+
+class Profiler {
+public:
+    bool enabled = false;
+    void begin(const char* name, hipStream_t s);
+    void end(const char* name, hipStream_t s);
+    void clear();
+    void read(const std::string& name, double* ms, int64_t* launches);
+    ~Profiler();
+private:
+    std::vector<hipEvent_t> pool_;
+    std::map<std::string, std::vector<std::pair<hipEvent_t, hipEvent_t>>> open_;
+    std::map<std::string, hipEvent_t> pending_;
+    hipEvent_t get();
+};
+
+// Key of a contraction pass for the tile table: (prec, rows, nk, B, G-per-rhs).
+struct PassKey {
+    int prec; int rows; int64_t nk; int64_t B; int64_t g;
+    bool operator<(const PassKey& o) const {
+        if (prec != o.prec) return prec < o.prec;
+        if (rows != o.rows) return rows < o.rows;
+        if (nk != o.nk) return nk < o.nk;
+        if (B != o.B) return B < o.B;
+        return g < o.g;
+    }
+};
+
+}  // namespace cola
+
+struct cola_op_s {
+    int device = 0;
+    int prec = COLA_PREC_FP64;
+    std::vector<cola::SysInfo> sys;
+    int64_t n_total = 0, nmax = 0;
+    int Jmax = 1;
+    int64_t fac_elems = 0, diag_elems = 0;
+    double* fac64 = nullptr;
+    float* fac32 = nullptr;
+    __bf16* facbf = nullptr;        // nsplit planes of fac_elems
+    int nsplit = 0;
+    double* diag64 = nullptr;
+    float* diag32 = nullptr;
+    cola::Workspace ws;
+    cola::Profiler prof;
+    std::map<cola::PassKey, cola::TileCfg> tiles;
+    double* grad_buf = nullptr;     // split-K slices of factor gradients that exceed the workspace
+    size_t grad_buf_elems = 0;
+};
+
+namespace cola {
+// Allocate (or keep) the per-op workspace for nrhs right-hand sides.
+int32_t ensure_workspace(cola_op_s* op, int nrhs, hipStream_t st);
+}

@@ -1,0 +1,267 @@
+"""Python face of libcola: operator handle, solve, and the autograd Function.
+
+PyTorch supplies device memory and the stream; every step of the MVM, the
+CG iteration, the refinement and the gradients runs in the HIP library.
+Vectors are packed: system s with n_s unknowns and nrhs right-hand sides
+occupies nrhs * n_s consecutive float64 entries (right-hand side r at
+offset r * n_s), systems one after another.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+def _stream_ptr(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _dev_f64(t: torch.Tensor) -> torch.Tensor:
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    return t.detach().to(torch.float64).contiguous()
+
+
+@dataclass
+class SystemSpec:
+    """One system: factors[j][k] (n_k x n_k float64 device tensors), optional diag, sigma2."""
+    factors: List[List[torch.Tensor]]
+    sigma2: float = 0.0
+    diag: Optional[torch.Tensor] = None
+
+    @property
+    def dims(self):
+        return tuple(int(f.shape[0]) for f in self.factors[0])
+
+    @property
+    def n(self) -> int:
+        return int(np.prod(self.dims))
+
+
+class KronOperator:
+    """A = sum_j kron(factors[j]) + diag(d) + sigma2 I for each system (cola_op_create)."""
+
+    def __init__(self, systems: Sequence[SystemSpec], prec: str = "fp32", stream=None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("KronOperator needs a ROCm GPU; there is no CPU path")
+        self.lib = L.lib()
+        self.prec = L.PREC_BY_NAME[prec]
+        self.systems = list(systems)
+        self._keep = []
+        descs = (L.SystemDesc * len(self.systems))()
+        for i, s in enumerate(self.systems):
+            J, F = len(s.factors), len(s.factors[0])
+            fac = [_dev_f64(f) for row in s.factors for f in row]
+            self._keep += fac
+            arr = (ctypes.c_void_p * (J * F))(*[f.data_ptr() for f in fac])
+            self._keep.append(arr)
+            d = descs[i]
+            d.nterms, d.nfactors = J, F
+            for k in range(F):
+                d.dims[k] = int(s.factors[0][k].shape[0])
+            d.factors = ctypes.cast(arr, ctypes.POINTER(ctypes.c_void_p))
+            if s.diag is not None:
+                dg = _dev_f64(s.diag).reshape(-1)
+                self._keep.append(dg)
+                d.diag = dg.data_ptr()
+            else:
+                d.diag = None
+            d.sigma2 = float(s.sigma2)
+        self._descs = descs
+        h = ctypes.c_void_p()
+        L.check("cola_op_create", self.lib.cola_op_create(descs, len(self.systems), self.prec,
+                                                           _stream_ptr(stream), ctypes.byref(h)))
+        self.handle = h
+        torch.cuda.current_stream().synchronize()
+        self._keep = []          # the library holds its own copies now
+        self.sizes = [s.n for s in self.systems]
+        self.n_total = int(sum(self.sizes))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.cola_op_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- packing helpers -------------------------------------------------
+    def pack(self, per_system: Sequence[torch.Tensor]) -> torch.Tensor:
+        """(nrhs, n_s) tensors per system -> one packed float64 device vector."""
+        return torch.cat([t.to(torch.float64).reshape(-1) for t in per_system]).contiguous()
+
+    def unpack(self, packed: torch.Tensor, nrhs: int) -> List[torch.Tensor]:
+        out, off = [], 0
+        for n in self.sizes:
+            out.append(packed[off:off + nrhs * n].view(nrhs, n))
+            off += nrhs * n
+        return out
+
+    # ---- entry points ----------------------------------------------------
+    def matvec(self, X: torch.Tensor, nrhs: int, prec: Optional[str] = None) -> torch.Tensor:
+        p = self.prec if prec is None else L.PREC_BY_NAME[prec]
+        dtype = L.COLA_F64 if p == L.COLA_PREC_FP64 else L.COLA_F32
+        tdt = torch.float64 if dtype == L.COLA_F64 else torch.float32
+        if X.dtype != tdt or not X.is_contiguous():
+            raise ValueError(f"X must be a contiguous {tdt} device tensor")
+        Y = torch.empty_like(X)
+        L.check("cola_kron_matvec", self.lib.cola_kron_matvec(self.handle, X.data_ptr(), Y.data_ptr(), nrhs,
+                                                              dtype, p, _stream_ptr()))
+        return Y
+
+    def _opts(self, tol, max_iters, prec, inner_tol, max_sweeps, check_every) -> L.SolveOpts:
+        o = L.SolveOpts()
+        o.tol = float(tol)
+        o.max_iters = int(max_iters)
+        o.prec = self.prec if prec is None else L.PREC_BY_NAME[prec]
+        o.inner_tol = float(inner_tol)
+        o.max_sweeps = int(max_sweeps)
+        o.check_every = int(check_every)
+        return o
+
+    def solve(self, B: torch.Tensor, nrhs: int, tol: float = 1e-6, max_iters: int = 10000,
+              prec: Optional[str] = None, inner_tol: float = 1e-4, max_sweeps: int = 20,
+              check_every: int = 32, info: Optional[torch.Tensor] = None):
+        """X = A^{-1} B (cola_cg_solve); returns (X, info tensor on device)."""
+        if B.dtype != torch.float64 or not B.is_contiguous():
+            raise ValueError("B must be a contiguous float64 device tensor")
+        X = torch.empty_like(B)
+        if info is None:
+            info = torch.empty(len(self.sizes) * nrhs * 6, dtype=torch.int32, device=B.device)
+        o = self._opts(tol, max_iters, prec, inner_tol, max_sweeps, check_every)
+        L.check("cola_cg_solve", self.lib.cola_cg_solve(self.handle, B.data_ptr(), X.data_ptr(), nrhs,
+                                                        ctypes.byref(o), info.data_ptr(), _stream_ptr()))
+        return X, info
+
+    def solve_backward(self, X: torch.Tensor, G: torch.Tensor, nrhs: int, tol: float = 1e-6,
+                       max_iters: int = 10000, prec: Optional[str] = None, inner_tol: float = 1e-4,
+                       max_sweeps: int = 20, check_every: int = 32, want_factors: bool = True,
+                       want_diag: bool = True):
+        """Adjoint backward (cola_cg_solve_backward): Lambda, dfactors, ddiag, dsigma2, info."""
+        dev = X.device
+        Lam = torch.empty_like(X)
+        dfac = []
+        ptrs = []
+        for s in self.systems:
+            rows = []
+            for row in s.factors:
+                r = []
+                for f in row:
+                    t = torch.empty(f.shape, dtype=torch.float64, device=dev)
+                    r.append(t)
+                    ptrs.append(t.data_ptr())
+                rows.append(r)
+            dfac.append(rows)
+        ddiag = []
+        dptrs = []
+        for s in self.systems:
+            if s.diag is not None and want_diag:
+                t = torch.empty(s.n, dtype=torch.float64, device=dev)
+                ddiag.append(t)
+                dptrs.append(t.data_ptr())
+            else:
+                ddiag.append(None)
+                dptrs.append(None)
+        ds2 = torch.empty(len(self.systems), dtype=torch.float64, device=dev)
+        info = torch.empty(len(self.sizes) * nrhs * 6, dtype=torch.int32, device=dev)
+        o = self._opts(tol, max_iters, prec, inner_tol, max_sweeps, check_every)
+        fa = (ctypes.c_void_p * max(1, len(ptrs)))(*ptrs) if want_factors else None
+        da = (ctypes.c_void_p * len(dptrs))(*dptrs)
+        L.check("cola_cg_solve_backward", self.lib.cola_cg_solve_backward(
+            self.handle, X.data_ptr(), G.data_ptr(), nrhs, ctypes.byref(o), Lam.data_ptr(),
+            ctypes.cast(fa, ctypes.POINTER(ctypes.c_void_p)) if fa is not None else None,
+            ctypes.cast(da, ctypes.POINTER(ctypes.c_void_p)), ds2.data_ptr(), info.data_ptr(), _stream_ptr()))
+        return Lam, (dfac if want_factors else None), ddiag, ds2, info
+
+    def autotune(self, nrhs: int):
+        L.check("cola_autotune", self.lib.cola_autotune(self.handle, nrhs, _stream_ptr()))
+
+    def profile_enable(self, on: bool = True):
+        L.check("cola_profile_enable", self.lib.cola_profile_enable(self.handle, 1 if on else 0))
+
+    def profile_read(self, kernel: str):
+        ms = ctypes.c_double()
+        cnt = ctypes.c_int64()
+        L.check("cola_profile_read", self.lib.cola_profile_read(self.handle, kernel.encode(), ctypes.byref(ms),
+                                                                ctypes.byref(cnt)))
+        return ms.value, cnt.value
+
+
+def decode_info(info: torch.Tensor, count: int):
+    """Device info buffer -> list of dicts (status, iters, sweeps, relres)."""
+    raw = info.detach().cpu().numpy().view(np.uint8)[: count * 24]
+    rec = np.frombuffer(raw.tobytes(), dtype=np.dtype([("status", "<i4"), ("iters", "<i4"), ("sweeps", "<i4"),
+                                                        ("reserved", "<i4"), ("relres", "<f8")]))
+    return [dict(status=int(r["status"]), iters=int(r["iters"]), sweeps=int(r["sweeps"]),
+                 relres=float(r["relres"])) for r in rec]
+
+
+class KronSolve(torch.autograd.Function):
+    """x = A^{-1} b with the adjoint backward of App. B.2 (rule 1).
+
+    forward(meta, B_packed, sigma2 (nsys), *tensors) where tensors are every
+    factor (system, term, factor order) followed by every diagonal present.
+    The backward runs a second solve for Lambda and the factor contractions
+    inside libcola; gradients flow on to whatever built the factors (e.g. an
+    RBF lengthscale) through torch's autograd.
+    """
+
+    @staticmethod
+    def forward(ctx, meta, B, sigma2, *tensors):
+        specs, opts = meta["specs"], meta["opts"]
+        it = iter(tensors)
+        systems = []
+        for i, (J, F, has_diag) in enumerate(specs):
+            facs = [[next(it) for _ in range(F)] for _ in range(J)]
+            systems.append([facs, has_diag])
+        diags = [next(it) if has_diag else None for (_, _, has_diag) in specs]
+        sys_specs = [SystemSpec(factors=f, sigma2=float(sigma2[i]), diag=diags[i])
+                     for i, (f, _) in enumerate(systems)]
+        op = KronOperator(sys_specs, prec=opts.get("prec", "fp32"))
+        nrhs = meta["nrhs"]
+        X, info = op.solve(B.detach().to(torch.float64).contiguous(), nrhs, **opts)
+        ctx.op = op
+        ctx.meta = meta
+        ctx.save_for_backward(X)
+        ctx.info = info
+        return X
+
+    @staticmethod
+    def backward(ctx, gX):
+        (X,) = ctx.saved_tensors
+        op, meta = ctx.op, ctx.meta
+        opts = dict(meta["opts"])
+        opts.update(meta.get("backward_opts", {}))
+        Lam, dfac, ddiag, ds2, info = op.solve_backward(X, gX.contiguous().to(torch.float64), meta["nrhs"], **opts)
+        ctx.backward_info = info
+        grads = [None, Lam, ds2]
+        for s in dfac:
+            for row in s:
+                grads.extend(row)
+        for (J, F, has_diag), dd in zip(meta["specs"], ddiag):
+            if has_diag:
+                grads.append(dd)
+        op.close()
+        return tuple(grads)
+
+
+def kron_cg_solve(systems: Sequence[SystemSpec], B: torch.Tensor, nrhs: int, **opts) -> torch.Tensor:
+    """Differentiable packed solve X = A^{-1} B over all systems."""
+    specs = [(len(s.factors), len(s.factors[0]), s.diag is not None) for s in systems]
+    backward_opts = opts.pop("backward_opts", {})
+    meta = {"specs": specs, "opts": opts, "nrhs": nrhs, "backward_opts": backward_opts}
+    sig = [s.sigma2 for s in systems]
+    sigma2 = torch.stack([torch.as_tensor(v, dtype=torch.float64, device=B.device) for v in sig])
+    tensors = [f for s in systems for row in s.factors for f in row]
+    tensors += [s.diag for s in systems if s.diag is not None]
+    return KronSolve.apply(meta, B, sigma2, *tensors)

@@ -1,0 +1,124 @@
+"""GPU parity of cola_cg_solve (plain FP64 CG and mixed-precision refinement) against the oracle."""
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import cg as ocg
+from oracle import direct, kron
+
+pytestmark = pytest.mark.gpu
+
+
+def _solve(systems, Bs, prec, nrhs, **kw):
+    from gpu_util import infos, make_op, pack, unpack
+    op = make_op(systems, prec="fp32" if prec == "fp64" else prec)
+    X, info = op.solve(pack(Bs), nrhs, prec=prec, **kw)
+    out = unpack(X, systems, nrhs), infos(info, len(systems) * nrhs)
+    op.close()
+    return out
+
+
+def test_fp64_cg_c1_recipe_reduced():
+    w = wl.config1(m=24)
+    s = w.systems[0]
+    (X,), info = _solve(w.systems, w.B, "fp64", 1, tol=1e-10, max_iters=3000)
+    assert info[0]["status"] == 0
+    assert kron.relres(s.factors, X, w.B[0], s.sigma2)[0] <= 1e-10
+    xref = direct.cholesky_solve(s.factors, w.B[0], s.sigma2)
+    kappa = direct.condition_number(s.factors[0], s.sigma2)
+    assert np.linalg.norm(X - xref) <= 2 * kappa * 1e-10 * np.linalg.norm(xref)
+    # same recurrence as the oracle: iteration counts agree closely
+    ref = ocg.cg(lambda V: kron.mvm(s.factors, V, s.sigma2), w.B[0], 1e-10, 3000)
+    assert abs(info[0]["iters"] - int(ref.iters[0])) <= max(3, int(0.05 * ref.iters[0]))
+
+
+def test_fp64_cg_c1_full_size():
+    w = wl.config1()
+    s = w.systems[0]
+    (X,), info = _solve(w.systems, w.B, "fp64", 1, tol=1e-10, max_iters=2000)
+    assert info[0]["status"] == 0
+    assert kron.relres(s.factors, X, w.B[0], s.sigma2)[0] <= 1e-10
+    xref = direct.cholesky_solve(s.factors, w.B[0], s.sigma2)
+    assert np.linalg.norm(X - xref) <= 1e-6 * np.linalg.norm(xref)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_refined_c2_recipe_reduced(prec):
+    w = wl.config2(m=16, nrhs=4)
+    s = w.systems[0]
+    (X,), info = _solve(w.systems, w.B, prec, 4, tol=1e-6, max_iters=5000, inner_tol=1e-4, max_sweeps=40)
+    assert all(i["status"] == 0 for i in info), info
+    rr = kron.relres(s.factors, X, w.B[0], s.sigma2)
+    assert np.all(rr <= 1e-6), rr
+    xref = direct.kron_eig_solve(s.factors[0], w.B[0], s.sigma2)
+    kappa = direct.condition_number(s.factors[0], s.sigma2)
+    assert np.linalg.norm(X - xref) <= 2 * kappa * 1e-6 * np.linalg.norm(xref)
+    for i, r in zip(info, rr):
+        assert abs(i["relres"] - r) <= 1e-3 * r + 1e-15     # the library's own FP64 residual
+
+
+def test_refined_sum_of_kron_with_diag_bf16():
+    w = wl.config5(m=32, nterms=4, nrhs=3)
+    s = w.systems[0]
+    (X,), info = _solve(w.systems, w.B, "bf16", 3, tol=1e-6, max_iters=500, inner_tol=1e-2, max_sweeps=30)
+    assert all(i["status"] == 0 for i in info), info
+    assert np.all(kron.relres(s.factors, X, w.B[0], s.sigma2, s.diag) <= 1e-6)
+    xref = direct.cholesky_solve(s.factors, w.B[0], s.sigma2, s.diag)
+    assert np.linalg.norm(X - xref) <= 1e-4 * np.linalg.norm(xref)
+
+
+def test_refined_uneven_batch_fp32():
+    w = wl.config3(nsys=6, dmin=5, dmax=40)
+    (Xs), info = _solve(w.systems, w.B, "fp32", 1, tol=1e-8, max_iters=3000, inner_tol=1e-4, max_sweeps=30)
+    for s, X, B, i in zip(w.systems, Xs, w.B, info):
+        assert i["status"] == 0
+        assert kron.relres(s.factors, X, B, s.sigma2)[0] <= 1e-8
+        xref = direct.kron_eig_solve(s.factors[0], B, s.sigma2)
+        assert np.linalg.norm(X - xref) <= 2 * direct.condition_number(s.factors[0], s.sigma2) * 1e-8 * \
+            np.linalg.norm(xref)
+
+
+def test_status_edge_cases_match_oracle():
+    rng = np.random.default_rng(41)
+    s = wl.random_system(rng, (4, 6), sigma2=0.2)
+    n = s.n
+    B = rng.standard_normal((4, n))
+    B[0] = 0.0                       # zero right-hand side: x = 0, no iterations
+    B[1, 5] = np.nan                 # non-finite input
+    (X,), info = _solve([s], [B], "fp64", 4, tol=1e-12, max_iters=500)
+    ref = ocg.cg(lambda V: kron.mvm(s.factors, V, s.sigma2), B, 1e-12, 500)
+    assert info[0]["status"] == 0 and info[0]["iters"] == 0 and not X[0].any()
+    assert ref.status[0] == "ok"
+    assert info[1]["status"] == -3 and ref.status[1] == "nonfinite"
+    assert info[2]["status"] == 0 and info[3]["status"] == 0
+    # iteration limit: valid partial iterate, NOT_CONVERGED
+    (X1,), info1 = _solve([s], [B[2:3]], "fp64", 1, tol=1e-14, max_iters=2)
+    assert info1[0]["status"] == 1 and info1[0]["iters"] == 2 and np.all(np.isfinite(X1))
+    r1 = ocg.cg(lambda V: kron.mvm(s.factors, V, s.sigma2), B[2:3], 1e-14, 2)
+    assert np.allclose(X1, r1.X, rtol=1e-10, atol=1e-12)
+
+
+def test_indefinite_operator_reports_not_spd():
+    rng = np.random.default_rng(42)
+    K1 = np.diag([1.0, 2.0, -3.0])
+    K2 = wl.wishart_factor(rng, 4)
+    s = wl.System(factors=[[K1, K2]], sigma2=0.0)
+    B = rng.standard_normal((1, 12))
+    (X,), info = _solve([s], [B], "fp64", 1, tol=1e-12, max_iters=100)
+    ref = ocg.cg(lambda V: kron.mvm(s.factors, V, 0.0), B, 1e-12, 100)
+    assert ref.status[0] == "not_spd"
+    assert info[0]["status"] == -2
+
+
+def test_solve_is_deterministic():
+    w = wl.config2(m=12, nrhs=2)
+    a, ia = _solve(w.systems, w.B, "fp32", 2, tol=1e-6, max_iters=3000, inner_tol=1e-4, max_sweeps=20)
+    b, ib = _solve(w.systems, w.B, "fp32", 2, tol=1e-6, max_iters=3000, inner_tol=1e-4, max_sweeps=20)
+    assert np.array_equal(a[0], b[0]) and ia == ib
+
+
+def test_no_poll_mode_matches_polling_mode():
+    w = wl.config1(m=16)
+    a, ia = _solve(w.systems, w.B, "fp64", 1, tol=1e-10, max_iters=400, check_every=0)
+    b, ib = _solve(w.systems, w.B, "fp64", 1, tol=1e-10, max_iters=400, check_every=7)
+    assert np.array_equal(a[0], b[0]) and ia == ib
