@@ -38,11 +38,13 @@ FP32_MFMA_PEAK_TFLOPS = 157.3
 
 # Algorithmic HBM bytes per element of one right-hand side, per launch class
 # (FP32 working vectors, 4 bytes per word):
+#   slab23        : read r, p (direction formed on the fly), write T      3 words
+#                   (modes 3 and 2 fused per 64 x 64 slab in LDS)
 #   contract_rows : read r, p (direction formed on the fly), write T      3 words
 #   contract_mid  : read T, write T'                                        2 words
 #   contract_last : read T', r, p_old, write q, p_new                       5 words
 #   update        : read x, r, p, q, write x, r                             6 words
-BYTES_PER_ELEM = {"contract_rows": 12, "contract_mid": 8, "contract_last": 20, "update": 24}
+BYTES_PER_ELEM = {"slab23": 12, "contract_rows": 12, "contract_mid": 8, "contract_last": 20, "update": 24}
 
 
 def parse():
@@ -128,8 +130,6 @@ def main():
         ms, cnt = op.profile_read(name)
         if cnt:
             kern[name] = {"total_ms": ms, "launches": cnt, "avg_us": 1e3 * ms / cnt}
-    for name in ("contract_rows", "contract_mid", "contract_last"):
-        pass
     op.profile_enable(False)
     dom = max(kern, key=lambda k: kern[k]["total_ms"]) if kern else None
     roof = None

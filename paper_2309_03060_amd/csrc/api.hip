@@ -12,6 +12,7 @@
 
 #include "grad.h"
 #include "op.h"
+#include "slab.h"
 #include "vector.h"
 
 using namespace cola;
@@ -57,9 +58,12 @@ int64_t max_blocks_per_rhs(const cola_op_s* op) {
     return m;
 }
 
+void destroy_graphs(cola_op_s* op);
+
 int32_t ensure_ws(cola_op_s* op, int nrhs, hipStream_t st) {
     Workspace& w = op->ws;
     if (w.nrhs >= nrhs) return COLA_OK;
+    destroy_graphs(op);
     free_ws(w);
     const size_t vec = (size_t)nrhs * (size_t)op->nmax * sizeof(double);
     int32_t rc = COLA_OK;
@@ -139,7 +143,38 @@ int32_t enqueue_mvm(cola_op_s* op, const SysInfo& s, int prec, int nrhs, const v
     const void* in = X;
     int64_t in_tstride = 0;
     int buf = 0;
-    for (int k = s.Fv - 1; k >= 0; --k) {
+    int kstart = s.Fv - 1;
+    if (s.Fv == 3 && op->use_slab && slab_supported(prec, s.dims[1], s.dims[2])) {
+        // modes 3 and 2 of every term in one pass over n2 x n3 slabs
+        const size_t fb = (prec == COLA_PREC_FP64) ? 8 : 4;
+        SlabArgs sa;
+        std::memset(&sa, 0, sizeof(sa));
+        sa.nslabs = (int64_t)nrhs * s.dims[0];
+        sa.a_per_rhs = s.dims[0];
+        sa.n2 = (int32_t)s.dims[1];
+        sa.n3 = (int32_t)s.dims[2];
+        sa.nterms = s.J;
+        sa.pnew = Rpnew != nullptr;
+        sa.X = X;
+        sa.R = Rpnew;
+        sa.Y = op->ws.inter[0];
+        sa.y_tstride = tstride;
+        sa.K2 = (const char*)fac + (size_t)s.fac_off[1] * fb;
+        sa.K3 = (const char*)fac + (size_t)s.fac_off[2] * fb;
+        sa.k2_tstride = s.dims[1] * s.dims[1];
+        sa.k3_tstride = s.dims[2] * s.dims[2];
+        sa.cg = tmpl.cg;
+        sa.outer = tmpl.outer;
+        {
+            ProfScope ps(op->prof, "slab23", st);
+            HIP_TRY(launch_slab23(prec, sa, st));
+        }
+        in = op->ws.inter[0];
+        in_tstride = tstride;
+        buf = 1;
+        kstart = 0;
+    }
+    for (int k = kstart; k >= 0; --k) {
         PassArgs a = tmpl;
         const int64_t nk = s.dims[k];
         int64_t lead = 1, trail = 1;
@@ -151,7 +186,7 @@ int32_t enqueue_mvm(cola_op_s* op, const SysInfo& s, int prec, int nrhs, const v
         a.k_plane = k_plane;
         a.X = in;
         a.x_tstride = in_tstride;
-        a.pnew = (k == s.Fv - 1) && Rpnew != nullptr;
+        a.pnew = (k == s.Fv - 1) && Rpnew != nullptr;   // only the first pass forms the direction
         a.R = Rpnew;
         const bool rows = (k == s.Fv - 1);
         if (rows) {
@@ -210,28 +245,147 @@ int32_t poll_flag(cola_op_s* op, const int32_t* dev, hipStream_t st, int32_t* ou
     return COLA_OK;
 }
 
-// CG iterations on prepared state: x, r, p, q are the working vectors.
+// One CG iteration on prepared state (x, r, p, q are the working vectors):
+// the MVM passes (direction update fused into the first and last pass) and
+// the vector update.
+template <typename T>
+int32_t enqueue_iteration(cola_op_s* op, const SysInfo& s, int prec, int nrhs, T* x, T* r, T* p, T* q,
+                          hipStream_t st) {
+    Workspace& w = op->ws;
+    PassArgs a = base_args(op);
+    a.cg = w.cg;
+    a.epi = EPI_CG;
+    a.Ep = p;
+    a.Er = r;
+    a.Epout = p;
+    int32_t rc = enqueue_mvm(op, s, prec, nrhs, p, r, q, a, st);
+    if (rc != COLA_OK) return rc;
+    ProfScope ps(op->prof, "update", st);
+    HIP_TRY(cg_update<T>(x, r, p, q, s.n, nrhs, w.cg, w.partials, (int)w.part_stride, w.counters, w.cnt, st));
+    return COLA_OK;
+}
+
+void destroy_graphs(cola_op_s* op) {
+    for (auto& kv : op->graphs) {
+        for (int b = 0; b < 2; ++b) {
+            if (kv.second.g[b].exec) (void)hipGraphExecDestroy(kv.second.g[b].exec);
+            for (auto& e : kv.second.g[b].ev) {
+                (void)hipEventDestroy(e.a);
+                (void)hipEventDestroy(e.b);
+            }
+            if (kv.second.done[b]) (void)hipEventDestroy(kv.second.done[b]);
+        }
+    }
+    op->graphs.clear();
+}
+
+// Capture `chunk` iterations into an executable graph (on the op's private
+// capture stream; nothing executes during capture).
+template <typename T>
+int32_t capture_chunk(cola_op_s* op, const SysInfo& s, int prec, int nrhs, T* x, T* r, T* p, T* q, int chunk,
+                      ChunkGraph* out) {
+    if (!op->cap_stream && hipStreamCreateWithFlags(&op->cap_stream, hipStreamNonBlocking) != hipSuccess)
+        return COLA_ERR_HIP;
+    if (hipStreamBeginCapture(op->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return COLA_ERR_HIP;
+    if (op->prof.enabled) op->prof.capture_list = &out->ev;
+    int32_t rc = COLA_OK;
+    for (int i = 0; i < chunk && rc == COLA_OK; ++i) rc = enqueue_iteration<T>(op, s, prec, nrhs, x, r, p, q, op->cap_stream);
+    op->prof.capture_list = nullptr;
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(op->cap_stream, &g);
+    if (rc != COLA_OK || e != hipSuccess || !g) {
+        if (g) (void)hipGraphDestroy(g);
+        (void)hipGetLastError();
+        return rc != COLA_OK ? rc : COLA_ERR_HIP;
+    }
+    const hipError_t ie = hipGraphInstantiate(&out->exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ie != hipSuccess) {
+        out->exec = nullptr;
+        (void)hipGetLastError();
+        return COLA_ERR_HIP;
+    }
+    return COLA_OK;
+}
+
+// CG iterations.  check_every == 0: enqueue max_iters iterations directly
+// (no host wait; safe under the caller's stream capture).  Otherwise the
+// iterations run as replays of two captured chunk graphs of check_every
+// iterations each; after launching chunk c the host waits for chunk c-1 and
+// reads its count of still-active right-hand sides, so the device always has
+// one chunk queued.  Iterations past convergence or past max_iters exit at
+// once on the device.
 template <typename T>
 int32_t run_cg(cola_op_s* op, const SysInfo& s, int prec, int nrhs, T* x, T* r, T* p, T* q, int max_iters,
                int check_every, hipStream_t st) {
     Workspace& w = op->ws;
-    for (int it = 0; it < max_iters; ++it) {
-        if (check_every > 0 && it > 0 && it % check_every == 0) {
-            int32_t active = 0;
-            int32_t rc = poll_flag(op, &w.cnt->num_active, st, &active);
+    if (check_every <= 0) {
+        for (int it = 0; it < max_iters; ++it) {
+            int32_t rc = enqueue_iteration<T>(op, s, prec, nrhs, x, r, p, q, st);
             if (rc != COLA_OK) return rc;
-            if (active <= 0) break;
         }
-        PassArgs a = base_args(op);
-        a.cg = w.cg;
-        a.epi = EPI_CG;
-        a.Ep = p;
-        a.Er = r;
-        a.Epout = p;
-        int32_t rc = enqueue_mvm(op, s, prec, nrhs, p, r, q, a, st);
-        if (rc != COLA_OK) return rc;
-        ProfScope ps(op->prof, "update", st);
-        HIP_TRY(cg_update<T>(x, r, p, q, s.n, nrhs, w.cg, w.partials, (int)w.part_stride, w.counters, w.cnt, st));
+        return COLA_OK;
+    }
+    const int chunk = std::min(check_every, max_iters);
+    GraphSet* gs = nullptr;
+    if (op->graphs_ok) {
+        GraphKey key{&s, prec, nrhs, x, r, p, q, chunk, op->prof.enabled ? 1 : 0, op->tiles_version};
+        auto it = op->graphs.find(key);
+        if (it == op->graphs.end()) {
+            GraphSet set;
+            int32_t rc = COLA_OK;
+            for (int b = 0; b < 2 && rc == COLA_OK; ++b) {
+                rc = capture_chunk<T>(op, s, prec, nrhs, x, r, p, q, chunk, &set.g[b]);
+                if (rc == COLA_OK && hipEventCreateWithFlags(&set.done[b], hipEventDisableTiming) != hipSuccess)
+                    rc = COLA_ERR_HIP;
+            }
+            if (rc == COLA_OK) {
+                it = op->graphs.emplace(key, set).first;
+            } else {
+                for (int b = 0; b < 2; ++b) {
+                    if (set.g[b].exec) (void)hipGraphExecDestroy(set.g[b].exec);
+                    for (auto& e : set.g[b].ev) {
+                        (void)hipEventDestroy(e.a);
+                        (void)hipEventDestroy(e.b);
+                    }
+                    if (set.done[b]) (void)hipEventDestroy(set.done[b]);
+                }
+                op->graphs_ok = false;     // fall back to direct launches from now on
+            }
+        }
+        if (it != op->graphs.end()) gs = &it->second;
+    }
+    const int nchunks = (max_iters + chunk - 1) / chunk;
+    if (!gs) {
+        for (int it = 0; it < nchunks * chunk; ++it) {
+            if (it > 0 && it % chunk == 0) {
+                int32_t active = 0;
+                int32_t rc = poll_flag(op, &w.cnt->num_active, st, &active);
+                if (rc != COLA_OK) return rc;
+                if (active <= 0) break;
+            }
+            int32_t rc = enqueue_iteration<T>(op, s, prec, nrhs, x, r, p, q, st);
+            if (rc != COLA_OK) return rc;
+        }
+        return COLA_OK;
+    }
+    int last = -1;
+    for (int c = 0; c < nchunks; ++c) {
+        const int b = c & 1;
+        HIP_TRY(hipGraphLaunch(gs->g[b].exec, st));
+        HIP_TRY(hipMemcpyAsync(&w.host_flag[b], &w.cnt->num_active, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipEventRecord(gs->done[b], st));
+        last = c;
+        if (c >= 1) {
+            const int pb = (c - 1) & 1;
+            HIP_TRY(hipEventSynchronize(gs->done[pb]));
+            if (op->prof.enabled) op->prof.harvest(gs->g[pb].ev);
+            if (*(volatile int32_t*)&w.host_flag[pb] <= 0) break;
+        }
+    }
+    if (last >= 0) {
+        HIP_TRY(hipEventSynchronize(gs->done[last & 1]));
+        if (op->prof.enabled) op->prof.harvest(gs->g[last & 1].ev);
     }
     return COLA_OK;
 }
@@ -448,6 +602,8 @@ int32_t cola_op_create(const cola_system_desc* systems, int32_t nsys, int32_t pr
 int32_t cola_op_destroy(cola_op_t op) {
     if (!op) return COLA_OK;
     (void)hipDeviceSynchronize();
+    destroy_graphs(op);
+    if (op->cap_stream) (void)hipStreamDestroy(op->cap_stream);
     free_ws(op->ws);
     void* ptrs[] = {op->fac64, op->fac32, op->facbf, op->diag64, op->diag32, op->grad_buf};
     for (void* p : ptrs)
@@ -559,44 +715,67 @@ hipEvent_t Profiler::get() {
     return e;
 }
 
+// Inside a stream capture an event is recorded as an external event-record
+// node (a plain record would only become a dependency edge of the graph).
+static void record_event(hipEvent_t e, hipStream_t s, bool capturing) {
+    if (capturing) (void)hipEventRecordWithFlags(e, s, hipEventRecordExternal);
+    else (void)hipEventRecord(e, s);
+}
+
 void Profiler::begin(const char* name, hipStream_t s) {
-    hipEvent_t e = get();
-    (void)hipEventRecord(e, s);
+    hipEvent_t e = capture_list ? nullptr : get();
+    if (capture_list) (void)hipEventCreate(&e);       // owned by the graph being captured
+    record_event(e, s, capture_list != nullptr);
     pending_[name] = e;
 }
 
 void Profiler::end(const char* name, hipStream_t s) {
     auto it = pending_.find(name);
     if (it == pending_.end()) return;
-    hipEvent_t e = get();
-    (void)hipEventRecord(e, s);
-    open_[name].push_back({it->second, e});
+    hipEvent_t e = nullptr;
+    if (capture_list) (void)hipEventCreate(&e);
+    else e = get();
+    record_event(e, s, capture_list != nullptr);
+    ProfPair pr{name, it->second, e};
+    if (capture_list) capture_list->push_back(pr);
+    else open_.push_back(pr);
     pending_.erase(it);
 }
 
-void Profiler::read(const std::string& name, double* ms, int64_t* launches) {
-    *ms = 0.0;
-    *launches = 0;
-    auto it = open_.find(name);
-    if (it == open_.end()) return;
-    for (auto& pr : it->second) {
+void Profiler::harvest(const std::vector<ProfPair>& pairs) {
+    for (const ProfPair& pr : pairs) {
         float t = 0.f;
-        if (hipEventElapsedTime(&t, pr.first, pr.second) == hipSuccess) {
-            *ms += t;
-            *launches += 1;
+        if (hipEventElapsedTime(&t, pr.a, pr.b) == hipSuccess) {
+            auto& tot = totals_[pr.name];
+            tot.first += t;
+            tot.second += 1;
+        } else {
+            (void)hipGetLastError();
         }
     }
 }
 
+void Profiler::read(const std::string& name, double* ms, int64_t* launches) {
+    harvest(open_);
+    for (auto& pr : open_) {
+        pool_.push_back(pr.a);
+        pool_.push_back(pr.b);
+    }
+    open_.clear();
+    auto it = totals_.find(name);
+    *ms = it == totals_.end() ? 0.0 : it->second.first;
+    *launches = it == totals_.end() ? 0 : it->second.second;
+}
+
 void Profiler::clear() {
-    for (auto& kv : open_)
-        for (auto& pr : kv.second) {
-            pool_.push_back(pr.first);
-            pool_.push_back(pr.second);
-        }
+    for (auto& pr : open_) {
+        pool_.push_back(pr.a);
+        pool_.push_back(pr.b);
+    }
     open_.clear();
     for (auto& kv : pending_) pool_.push_back(kv.second);
     pending_.clear();
+    totals_.clear();
 }
 
 Profiler::~Profiler() {

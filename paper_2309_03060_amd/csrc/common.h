@@ -83,20 +83,30 @@ __device__ inline void store_coherent(double* p, double v) {
 // returns true (in all its threads) with the total in *total.  The counter
 // is reset by that block so the next launch starts from zero.  No block ever
 // waits for another, so the pattern cannot hang.
+//
+// Ordering without cache-wide fences: the partial is written with a relaxed
+// device-scope atomic store (a coherent store that does not stay in this
+// XCD's L2), the issuing thread waits for that store to complete, and only
+// then increments the counter with a relaxed device-scope atomic.  The last
+// block reads the partials with coherent atomic loads issued after it has
+// seen the final count.  A release/acquire fence at device scope would
+// instead write back and invalidate the whole L2 of the XCD from every
+// block, which dominated the run time of the streaming kernels.
 __device__ inline bool last_block_reduce(double partial, double* partials, uint32_t* counter,
                                          int nblocks, int myblock, double* total,
                                          double* smem) {
     __shared__ int s_last;
     if (threadIdx.x == 0) {
         store_coherent(&partials[myblock], partial);
-        __atomic_thread_fence(__ATOMIC_RELEASE);  // publish before counting (device scope)
-        uint32_t prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL,
-                                               __HIP_MEMORY_SCOPE_AGENT);
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        __builtin_amdgcn_s_waitcnt(0);            // the partial store has completed
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        const uint32_t prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT);
         s_last = (prev == (uint32_t)(nblocks - 1));
     }
     __syncthreads();
     if (!s_last) return false;
-    __atomic_thread_fence(__ATOMIC_ACQUIRE);
     double s = 0.0;
     for (int i = threadIdx.x; i < nblocks; i += blockDim.x) s += load_coherent(&partials[i]);
     s = block_sum(s, smem);

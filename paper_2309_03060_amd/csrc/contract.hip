@@ -79,19 +79,49 @@ __device__ inline bool gate_of(const PassArgs& a, int64_t rhs) {
     return true;
 }
 
+// 4 consecutive elements (the address is a multiple of 4 elements).
+__device__ inline void load4(const float* p, float* o) {
+    const floatx4 v = *(const floatx4*)p;
+    o[0] = v[0]; o[1] = v[1]; o[2] = v[2]; o[3] = v[3];
+}
+__device__ inline void load4(const double* p, double* o) {
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    const d2 a = *(const d2*)p, b = *(const d2*)(p + 2);
+    o[0] = a[0]; o[1] = a[1]; o[2] = b[0]; o[3] = b[1];
+}
+__device__ inline void load4(const __bf16* p, __bf16* o) {
+    typedef __bf16 b4 __attribute__((ext_vector_type(4)));
+    const b4 v = *(const b4*)p;
+    o[0] = v[0]; o[1] = v[1]; o[2] = v[2]; o[3] = v[3];
+}
+__device__ inline void store4(float* p, const float* v) { *(floatx4*)p = floatx4{v[0], v[1], v[2], v[3]}; }
+__device__ inline void store4(double* p, const double* v) {
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    *(d2*)p = d2{v[0], v[1]};
+    *(d2*)(p + 2) = d2{v[2], v[3]};
+}
+
 template <class P, int WM, int WN, bool ROWS>
 __global__ __launch_bounds__(kThreads) void k_contract(PassArgs a) {
     using V = typename P::V; using Fac = typename P::Fac; using L = typename P::L;
     using Acc = typename P::Acc;
     constexpr int MT = 32 * WM, NT = 32 * WN, KT = P::KT, KP = P::KP, NS = P::NS;
-    __shared__ __attribute__((aligned(16))) L As[NS][MT * KP];
-    __shared__ __attribute__((aligned(16))) L Bs[NS][NT * KP];
+    constexpr int EPAD = sizeof(V) == 8 ? 2 : 4;
+    constexpr int EW = 16 * WN + EPAD;                       // epilogue row stride (elements)
+    constexpr size_t AB_BYTES = sizeof(L) * NS * (size_t)(MT + NT) * KP;
+    constexpr size_t E_BYTES = sizeof(V) * 4 * 16 * (size_t)EW;
+    constexpr size_t SMEM = AB_BYTES > E_BYTES ? AB_BYTES : E_BYTES;
+    __shared__ __attribute__((aligned(16))) char smem[SMEM];
     __shared__ double red[4];
+    L* As = (L*)smem;                      // [NS][MT][KP]
+    L* Bs = As + NS * MT * KP;             // [NS][NT][KP]
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
     const int nk = a.nk;
     const int64_t k_plane = a.k_plane;
+    const bool kvec = (nk % 4) == 0;                       // factor rows / ROWS vectors load 4-wide
+    const bool bvec = (a.B % 4) == 0;                      // COLS vectors load 4-wide
 
     int64_t g = 0, m0, n0, nBt = 1;
     int nMt = 1, tout;
@@ -122,9 +152,32 @@ __global__ __launch_bounds__(kThreads) void k_contract(PassArgs a) {
 #pragma unroll
         for (int j = 0; j < WN; ++j) acc[i][j] = Acc{0, 0, 0, 0};
 
-    // beta of the CG direction update for COLS (one batch per block)
     double beta_blk = 0.0;
     if (!ROWS && a.pnew) beta_blk = a.cg[g / a.a_per_rhs].beta;
+
+    // stage a k-contiguous [rows][KT] tile of a factor (4 elements per step)
+    auto stage_factor = [&](L* dst, const Fac* Kp, int64_t r0, int rows, int k0) {
+        for (int e = tid; e < rows * (KT / 4); e += kThreads) {
+            const int m = e / (KT / 4), k = (e % (KT / 4)) * 4;
+            const int64_t gm = r0 + m;
+            const int gk = k0 + k;
+#pragma unroll
+            for (int sp = 0; sp < NS; ++sp) {
+                Fac f[4] = {(Fac)0.0f, (Fac)0.0f, (Fac)0.0f, (Fac)0.0f};
+                if (gm < nk) {
+                    const Fac* src = Kp + sp * k_plane + gm * nk + gk;
+                    if (kvec && gk + 3 < nk) {
+                        load4(src, f);
+                    } else {
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) if (gk + c < nk) f[c] = src[c];
+                    }
+                }
+#pragma unroll
+                for (int c = 0; c < 4; ++c) dst[(sp * rows + m) * KP + k + c] = (L)f[c];
+            }
+        }
+    };
 
     for (int t = 0; t < a.nsum; ++t) {
         const int tt = (a.nsum > 1) ? t : tout;
@@ -132,55 +185,77 @@ __global__ __launch_bounds__(kThreads) void k_contract(PassArgs a) {
         const V* Xp = (const V*)a.X + (int64_t)tt * a.x_tstride;
         const V* Rp = (const V*)a.R + (int64_t)tt * a.x_tstride;
         for (int k0 = 0; k0 < nk; k0 += KT) {
-            // ---- stage A tile (MT x KT) ----
-            for (int e = tid; e < MT * KT; e += kThreads) {
-                const int m = e / KT, k = e % KT;
-                const int64_t gm = m0 + m;
-                const int gk = k0 + k;
-                L parts[NS];
-                if constexpr (ROWS) {
-                    V v = 0;
-                    if (gm < a.G && gk < nk) {
+            if constexpr (ROWS) {
+                // A: vector rows X[g, k] (k contiguous), B: factor rows K[i, k]
+                for (int e = tid; e < MT * (KT / 4); e += kThreads) {
+                    const int m = e / (KT / 4), k = (e % (KT / 4)) * 4;
+                    const int64_t gm = m0 + m;
+                    const int gk = k0 + k;
+                    V v[4] = {0, 0, 0, 0};
+                    if (gm < a.G) {
                         const int64_t idx = gm * nk + gk;
-                        v = Xp[idx];
-                        if (a.pnew) v = pnew_of(Rp[idx], v, a.cg[gm / a.a_per_rhs].beta);
+                        if (kvec && gk + 3 < nk) {
+                            load4(Xp + idx, v);
+                            if (a.pnew) {
+                                V rr[4];
+                                load4(Rp + idx, rr);
+                                const double be = a.cg[gm / a.a_per_rhs].beta;
+#pragma unroll
+                                for (int c = 0; c < 4; ++c) v[c] = pnew_of(rr[c], v[c], be);
+                            }
+                        } else {
+#pragma unroll
+                            for (int c = 0; c < 4; ++c)
+                                if (gk + c < nk) {
+                                    v[c] = Xp[idx + c];
+                                    if (a.pnew) v[c] = pnew_of(Rp[idx + c], v[c], a.cg[gm / a.a_per_rhs].beta);
+                                }
+                        }
                     }
-                    split_value<P>(v, parts);
-                } else {
-                    const bool in = (gm < nk && gk < nk);
 #pragma unroll
-                    for (int s = 0; s < NS; ++s)
-                        parts[s] = in ? (L)Kp[s * k_plane + gm * nk + gk] : (L)0.0f;
+                    for (int c = 0; c < 4; ++c) {
+                        L parts[NS];
+                        split_value<P>(v[c], parts);
+#pragma unroll
+                        for (int sp = 0; sp < NS; ++sp) As[(sp * MT + m) * KP + k + c] = parts[sp];
+                    }
                 }
-#pragma unroll
-                for (int s = 0; s < NS; ++s) As[s][m * KP + k] = parts[s];
-            }
-            // ---- stage B tile (NT x KT) ----
-            for (int e = tid; e < NT * KT; e += kThreads) {
-                L parts[NS];
-                int n, k;
-                if constexpr (ROWS) {
-                    n = e / KT; k = e % KT;
-                    const int64_t gn = n0 + n;
+                stage_factor(Bs, Kp, n0, NT, k0);
+            } else {
+                // A: factor rows K[i, k], B: vector X[g, k, b] (b contiguous) stored as [b][k]
+                stage_factor(As, Kp, m0, MT, k0);
+                for (int e = tid; e < KT * (NT / 4); e += kThreads) {
+                    const int k = e / (NT / 4), n = (e % (NT / 4)) * 4;
                     const int gk = k0 + k;
-                    const bool in = (gn < nk && gk < nk);
-#pragma unroll
-                    for (int s = 0; s < NS; ++s)
-                        parts[s] = in ? (L)Kp[s * k_plane + gn * nk + gk] : (L)0.0f;
-                } else {
-                    n = e % NT; k = e / NT;
                     const int64_t gn = n0 + n;
-                    const int gk = k0 + k;
-                    V v = 0;
-                    if (gn < a.B && gk < nk) {
+                    V v[4] = {0, 0, 0, 0};
+                    if (gk < nk) {
                         const int64_t idx = (g * nk + gk) * a.B + gn;
-                        v = Xp[idx];
-                        if (a.pnew) v = pnew_of(Rp[idx], v, beta_blk);
-                    }
-                    split_value<P>(v, parts);
-                }
+                        if (bvec && gn + 3 < a.B) {
+                            load4(Xp + idx, v);
+                            if (a.pnew) {
+                                V rr[4];
+                                load4(Rp + idx, rr);
 #pragma unroll
-                for (int s = 0; s < NS; ++s) Bs[s][n * KP + k] = parts[s];
+                                for (int c = 0; c < 4; ++c) v[c] = pnew_of(rr[c], v[c], beta_blk);
+                            }
+                        } else {
+#pragma unroll
+                            for (int c = 0; c < 4; ++c)
+                                if (gn + c < a.B) {
+                                    v[c] = Xp[idx + c];
+                                    if (a.pnew) v[c] = pnew_of(Rp[idx + c], v[c], beta_blk);
+                                }
+                        }
+                    }
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        L parts[NS];
+                        split_value<P>(v[c], parts);
+#pragma unroll
+                        for (int sp = 0; sp < NS; ++sp) Bs[(sp * NT + n + c) * KP + k] = parts[sp];
+                    }
+                }
             }
             __syncthreads();
             // ---- MFMA over the staged K slice ----
@@ -190,10 +265,10 @@ __global__ __launch_bounds__(kThreads) void k_contract(PassArgs a) {
                     L av[WM], bv[WN];
 #pragma unroll
                     for (int i = 0; i < WM; ++i)
-                        av[i] = As[0][(wm * WM * 16 + i * 16 + (lane & 15)) * KP + kk + (lane >> 4)];
+                        av[i] = As[(wm * WM * 16 + i * 16 + (lane & 15)) * KP + kk + (lane >> 4)];
 #pragma unroll
                     for (int j = 0; j < WN; ++j)
-                        bv[j] = Bs[0][(wn * WN * 16 + j * 16 + (lane & 15)) * KP + kk + (lane >> 4)];
+                        bv[j] = Bs[(wn * WN * 16 + j * 16 + (lane & 15)) * KP + kk + (lane >> 4)];
 #pragma unroll
                     for (int i = 0; i < WM; ++i)
 #pragma unroll
@@ -201,13 +276,15 @@ __global__ __launch_bounds__(kThreads) void k_contract(PassArgs a) {
                 } else {
                     bf16x8 av[NS][WM], bv[NS][WN];
 #pragma unroll
-                    for (int s = 0; s < NS; ++s) {
+                    for (int sp = 0; sp < NS; ++sp) {
 #pragma unroll
                         for (int i = 0; i < WM; ++i)
-                            av[s][i] = *(const bf16x8*)&As[s][(wm * WM * 16 + i * 16 + (lane & 15)) * KP + kk + 8 * (lane >> 4)];
+                            av[sp][i] = *(const bf16x8*)&As[(sp * MT + wm * WM * 16 + i * 16 + (lane & 15)) * KP + kk +
+                                                           8 * (lane >> 4)];
 #pragma unroll
                         for (int j = 0; j < WN; ++j)
-                            bv[s][j] = *(const bf16x8*)&Bs[s][(wn * WN * 16 + j * 16 + (lane & 15)) * KP + kk + 8 * (lane >> 4)];
+                            bv[sp][j] = *(const bf16x8*)&Bs[(sp * NT + wn * WN * 16 + j * 16 + (lane & 15)) * KP + kk +
+                                                           8 * (lane >> 4)];
                     }
 #pragma unroll
                     for (int i = 0; i < WM; ++i)
@@ -231,49 +308,87 @@ __global__ __launch_bounds__(kThreads) void k_contract(PassArgs a) {
         }
     }
 
-    // ---- epilogue ----
+    // ---- epilogue: each wave stages one 16-row slice of its sub-tile in LDS
+    // and then walks it 4 columns at a time, so global accesses are 16-byte
+    // vectors along the contiguous dimension ----
     double dot = 0.0;
     V* Y = (V*)a.Y + (int64_t)tout * a.y_tstride;
     double beta_e = 0.0;
     if (!ROWS && a.epi == EPI_CG) beta_e = a.cg[g].beta;
+    V* Ew = (V*)smem + wave * 16 * EW;
+    constexpr int CH = (16 * WN) / 4;                        // 4-column chunks per staged row
 #pragma unroll
-    for (int i = 0; i < WM; ++i)
+    for (int i = 0; i < WM; ++i) {
 #pragma unroll
         for (int j = 0; j < WN; ++j)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int64_t m = m0 + wm * WM * 16 + i * 16 + acc_row(acc[i][j][v], lane, v);
-                const int64_t n = n0 + wn * WN * 16 + j * 16 + (lane & 15);
-                const V val = (V)acc[i][j][v];
-                if constexpr (ROWS) {
-                    if (m < a.G && n < nk) Y[m * nk + n] = val;
+            for (int v = 0; v < 4; ++v)
+                Ew[acc_row(acc[i][j][v], lane, v) * EW + j * 16 + (lane & 15)] = (V)acc[i][j][v];
+        __syncthreads();
+        for (int t2 = lane; t2 < 16 * CH; t2 += 64) {
+            const int r = t2 / CH, c4 = (t2 % CH) * 4;
+            const int64_t m = m0 + wm * WM * 16 + i * 16 + r;
+            const int64_t n = n0 + wn * WN * 16 + c4;
+            V val[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) val[c] = Ew[r * EW + c4 + c];
+            if constexpr (ROWS) {
+                if (m < a.G) {
+                    V* dst = Y + m * nk + n;
+                    if (kvec && n + 3 < nk) store4(dst, val);
+                    else
+                        for (int c = 0; c < 4; ++c) if (n + c < nk) dst[c] = val[c];
+                }
+            } else if (m < nk) {
+                const int64_t e0 = m * a.B + n;
+                const int64_t idx = g * (int64_t)nk * a.B + e0;
+                const bool full = bvec && n + 3 < a.B;
+                const int cnt = full ? 4 : (int)((a.B - n) < 4 ? (a.B - n > 0 ? a.B - n : 0) : 4);
+                V out[4] = {val[0], val[1], val[2], val[3]};
+                if (a.epi == EPI_STORE) {
+                    if (full) store4(Y + idx, out);
+                    else for (int c = 0; c < cnt; ++c) Y[idx + c] = out[c];
                 } else {
-                    if (m < nk && n < a.B) {
-                        const int64_t e = m * a.B + n;
-                        const int64_t idx = g * (int64_t)nk * a.B + e;
-                        if (a.epi == EPI_STORE) {
-                            Y[idx] = val;
-                        } else {
-                            V dg = (V)a.sigma2;
-                            if (a.dvec) dg += ((const V*)a.dvec)[e];
-                            if (a.epi == EPI_CG) {
-                                const V pn = pnew_of(((const V*)a.Er)[idx], ((const V*)a.Ep)[idx], beta_e);
-                                const V q = val + dg * pn;
-                                Y[idx] = q;
-                                ((V*)a.Epout)[idx] = pn;
-                                dot += (double)pn * (double)q;
-                            } else if (a.epi == EPI_RESID) {
-                                const V x = ((const V*)a.Ep)[idx];
-                                const V r = ((const V*)a.Er)[idx] - (val + dg * x);
-                                Y[idx] = r;
-                                dot += (double)r * (double)r;
-                            } else {  // EPI_MATVEC
-                                Y[idx] = val + dg * ((const V*)a.Ep)[idx];
-                            }
+                    V dg[4], u[4], w4[4];
+                    for (int c = 0; c < 4; ++c) dg[c] = (V)a.sigma2;
+                    if (full) {
+                        if (a.dvec) { V d4[4]; load4((const V*)a.dvec + e0, d4); for (int c = 0; c < 4; ++c) dg[c] += d4[c]; }
+                        load4((const V*)a.Ep + idx, u);
+                        if (a.epi != EPI_MATVEC) load4((const V*)a.Er + idx, w4);
+                    } else {
+                        for (int c = 0; c < cnt; ++c) {
+                            if (a.dvec) dg[c] += ((const V*)a.dvec)[e0 + c];
+                            u[c] = ((const V*)a.Ep)[idx + c];
+                            if (a.epi != EPI_MATVEC) w4[c] = ((const V*)a.Er)[idx + c];
                         }
+                    }
+                    if (a.epi == EPI_CG) {
+                        V pn[4];
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) {
+                            pn[c] = pnew_of(w4[c], u[c], beta_e);     // r + beta p_old
+                            out[c] = val[c] + dg[c] * pn[c];
+                        }
+                        for (int c = 0; c < cnt; ++c) dot += (double)pn[c] * (double)out[c];
+                        if (full) { store4(Y + idx, out); store4((V*)a.Epout + idx, pn); }
+                        else for (int c = 0; c < cnt; ++c) { Y[idx + c] = out[c]; ((V*)a.Epout)[idx + c] = pn[c]; }
+                    } else if (a.epi == EPI_RESID) {
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) out[c] = w4[c] - (val[c] + dg[c] * u[c]);
+                        for (int c = 0; c < cnt; ++c) dot += (double)out[c] * (double)out[c];
+                        if (full) store4(Y + idx, out);
+                        else for (int c = 0; c < cnt; ++c) Y[idx + c] = out[c];
+                    } else {  // EPI_MATVEC
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) out[c] = val[c] + dg[c] * u[c];
+                        if (full) store4(Y + idx, out);
+                        else for (int c = 0; c < cnt; ++c) Y[idx + c] = out[c];
                     }
                 }
             }
+        }
+        __syncthreads();
+    }
 
     if constexpr (!ROWS) {
         if (a.epi == EPI_CG || a.epi == EPI_RESID) {

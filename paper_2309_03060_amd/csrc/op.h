@@ -1,6 +1,7 @@
 // Operator handle and workspace (host side of libcola).
 #pragma once
 #include <map>
+#include <tuple>
 #include <string>
 #include <utility>
 #include <vector>
@@ -39,19 +40,46 @@ struct Workspace {
     int32_t* host_flag = nullptr;     // pinned
 };
 
+// Per-kernel-class timing with HIP events recorded around launches.  Direct
+// launches keep their event pairs until read; launches captured into a
+// graph record into that graph's own event list, which is harvested after
+// every replay (a replay overwrites the events of the previous one).
+struct ProfPair { std::string name; hipEvent_t a, b; };
+
 class Profiler {
 public:
     bool enabled = false;
+    std::vector<ProfPair>* capture_list = nullptr;   // set while capturing a graph
     void begin(const char* name, hipStream_t s);
     void end(const char* name, hipStream_t s);
+    void harvest(const std::vector<ProfPair>& pairs);
     void clear();
     void read(const std::string& name, double* ms, int64_t* launches);
+    hipEvent_t get();
     ~Profiler();
 private:
     std::vector<hipEvent_t> pool_;
-    std::map<std::string, std::vector<std::pair<hipEvent_t, hipEvent_t>>> open_;
+    std::vector<ProfPair> open_;
     std::map<std::string, hipEvent_t> pending_;
-    hipEvent_t get();
+    std::map<std::string, std::pair<double, int64_t>> totals_;
+};
+
+// A captured chunk of CG iterations, replayed with hipGraphLaunch.
+struct ChunkGraph {
+    hipGraphExec_t exec = nullptr;
+    std::vector<ProfPair> ev;       // profiling events inside the graph
+};
+struct GraphSet {
+    ChunkGraph g[2];                // alternated so one chunk runs while the host polls the other
+    hipEvent_t done[2] = {nullptr, nullptr};
+};
+struct GraphKey {
+    const void* sys; int prec; int nrhs; const void* x; const void* r; const void* p; const void* q;
+    int chunk; int profiled; int tiles_version;
+    bool operator<(const GraphKey& o) const {
+        return std::tie(sys, prec, nrhs, x, r, p, q, chunk, profiled, tiles_version) <
+               std::tie(o.sys, o.prec, o.nrhs, o.x, o.r, o.p, o.q, o.chunk, o.profiled, o.tiles_version);
+    }
 };
 
 // Key of a contraction pass for the tile table: (prec, rows, nk, B, G-per-rhs).
@@ -86,6 +114,11 @@ struct cola_op_s {
     std::map<cola::PassKey, cola::TileCfg> tiles;
     double* grad_buf = nullptr;     // split-K slices of factor gradients that exceed the workspace
     size_t grad_buf_elems = 0;
+    int tiles_version = 0;          // bumped when the tile table changes (invalidates graphs)
+    bool graphs_ok = true;          // false after a capture failure: launch directly
+    bool use_slab = true;           // fuse modes 2 and 3 of three-mode terms when slabs fit in LDS
+    hipStream_t cap_stream = nullptr;
+    std::map<cola::GraphKey, cola::GraphSet> graphs;
 };
 
 namespace cola {
