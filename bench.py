@@ -103,7 +103,7 @@ def main():
     B = torch.tensor(w.B[0], device=dev).reshape(-1).contiguous()
     if args.autotune:
         op.autotune(nrhs)
-    opts = dict(tol=args.tol, max_iters=20000, prec="fp32", inner_tol=1e-4, max_sweeps=40, check_every=32)
+    opts = dict(tol=args.tol, max_iters=20000, prec="fp32", inner_tol=0.1, check_every=32, refine="reliable")
 
     for _ in range(args.warmup):
         op.solve(B, nrhs, **opts)
@@ -153,7 +153,9 @@ def main():
     tts = None
     if not args.no_tts:
         res = {}
-        for label, o in (("mixed_fp32_refined", dict(opts, tol=1e-6)),
+        for label, o in (("mixed_fp32_reliable", dict(opts, tol=1e-6)),
+                         ("mixed_fp32_restarted", dict(opts, tol=1e-6, refine="restart", inner_tol=1e-4,
+                                                       max_sweeps=60)),
                          ("fp64_cg", dict(tol=1e-6, max_iters=20000, prec="fp64", check_every=32))):
             torch.cuda.synchronize()
             t1 = time.perf_counter()
@@ -164,8 +166,9 @@ def main():
             res[label] = {"seconds": round(t, 4), "iters_max": max(r["iters"] for r in rec),
                           "relres_max": max(r["relres"] for r in rec),
                           "status": sorted({r["status"] for r in rec})}
-        res["speedup"] = round(res["fp64_cg"]["seconds"] / res["mixed_fp32_refined"]["seconds"], 3)
-        res["note"] = ("fp64_cg relres is its recursive residual; mixed relres is the FP64 true residual")
+        res["speedup"] = round(res["fp64_cg"]["seconds"] / res["mixed_fp32_reliable"]["seconds"], 3)
+        res["note"] = ("fp64_cg relres is its recursive residual; mixed relres is the FP64 true residual; "
+                       "speedup = fp64_cg seconds / mixed_fp32_reliable seconds")
         tts = res
 
     cpu = None
@@ -181,6 +184,7 @@ def main():
                                f"n={n}, {nrhs} RHS N(0,1), FP32 inner CG + FP64 refinement to true relres "
                                f"{args.tol:g}", "n": n, "nrhs": nrhs, "factor_dim": args.m,
                    "rhs_iters_per_step": rhs_iters // max(1, args.steps), "statuses": statuses,
+                   "mixed_scheme": "FP32 CG with FP64 reliable updates (delta 0.1)",
                    "worst_relres": worst, "parallelism": "single GPU"},
         "roofline": roof, "cpu_baseline": cpu, "mixed_vs_fp64": tts,
     }

@@ -103,18 +103,26 @@ int32_t cola_op_size(cola_op_t op, int64_t* n_total, int32_t* nsys);
 int32_t cola_kron_matvec(cola_op_t op, const void* X, void* Y, int32_t nrhs,
                          int32_t dtype, int32_t prec, void* stream);
 
+/* mixed-precision scheme (cola_solve_opts.refine) ------------------------ */
+#define COLA_REFINE_RELIABLE 0  /* one low-precision CG; its residual is replaced by the FP64 true
+                                   residual whenever it has dropped by inner_tol (reliable updates) */
+#define COLA_REFINE_RESTART  1  /* classical refinement: restarted inner CG solves to inner_tol,
+                                   FP64 residual between sweeps (at most max_sweeps sweeps)        */
+
 /* Solve options. */
 typedef struct {
     double  tol;          /* target relative residual ||b - A x|| / ||b|| per RHS, > 0 */
     int32_t max_iters;    /* max CG iterations per (inner) solve, >= 1                  */
     int32_t prec;         /* COLA_PREC_FP64, or the op's working precision              */
-    double  inner_tol;    /* relative residual target of each inner solve (refinement)  */
-    int32_t max_sweeps;   /* refinement sweeps when prec != FP64 (>= 1); ignored for FP64 */
+    double  inner_tol;    /* in (0, 1): residual reduction between reliable updates, or the
+                             relative residual target of each restarted inner solve       */
+    int32_t max_sweeps;   /* restarted refinement: sweeps (>= 1); otherwise ignored       */
     int32_t check_every;  /* >0: the host waits on the stream every this many CG
                              iterations to stop early once all RHS converged;
                              0: never wait - all work is enqueued (max_iters
                              iterations per sweep, device-side early exit), which
                              makes the call safe under stream capture           */
+    int32_t refine;       /* COLA_REFINE_RELIABLE or COLA_REFINE_RESTART (prec != FP64) */
 } cola_solve_opts;
 
 /* Per (system, RHS) outcome, written to DEVICE memory in stream order. */
@@ -122,7 +130,7 @@ typedef struct {
     int32_t status;       /* COLA_OK, COLA_NOT_CONVERGED, COLA_STAGNATED,
                              COLA_ERR_NOT_SPD or COLA_ERR_NONFINITE            */
     int32_t iters;        /* CG iterations summed over all sweeps               */
-    int32_t sweeps;       /* refinement sweeps (0 for a plain solve)            */
+    int32_t sweeps;       /* refinement sweeps or reliable updates (0 for a plain solve) */
     int32_t reserved;
     double  relres;       /* final relative residual: the FP64 true residual
                              when refining, the recursive one for a plain solve */
@@ -131,10 +139,14 @@ typedef struct {
 /* Solve A X = B for nrhs right-hand sides (packed, float64, device).
  *  - prec == COLA_PREC_FP64: textbook CG in FP64 to tol on the recursive
  *    residual, x0 = 0.
- *  - prec == the op's working precision: iterative refinement - the FP64
- *    residual r = b - A x is formed with the FP64 factors; CG in the working
- *    precision solves A d = r / ||r|| to inner_tol; x += ||r|| d in FP64;
- *    stops when the FP64 relative residual <= tol.
+ *  - prec == the op's working precision: mixed precision with an FP64
+ *    residual formed from the FP64 factors, stopping when the FP64 relative
+ *    residual <= tol.  refine == COLA_REFINE_RELIABLE (default): a single CG in
+ *    the working precision whose x is folded into the FP64 solution and whose
+ *    residual is replaced by the FP64 one every time it has dropped by
+ *    inner_tol (or has converged), keeping the search direction.
+ *    refine == COLA_REFINE_RESTART: each sweep solves A d = r / ||r|| from
+ *    scratch to inner_tol and updates x += ||r|| d in FP64.
  * Right-hand sides converge independently; the call ends when all have
  * converged or hit a limit (the multi-RHS semantics of the paper's block
  * solves, App. D.5).  info: device array of nsys*nrhs entries, or NULL.

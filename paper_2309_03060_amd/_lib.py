@@ -29,6 +29,10 @@ COLA_PREC_FP32 = 1
 COLA_PREC_BF16 = 2
 COLA_PREC_BF16X3 = 3
 
+COLA_REFINE_RELIABLE = 0
+COLA_REFINE_RESTART = 1
+REFINE_BY_NAME = {"reliable": COLA_REFINE_RELIABLE, "restart": COLA_REFINE_RESTART}
+
 PREC_BY_NAME = {"fp64": COLA_PREC_FP64, "fp32": COLA_PREC_FP32,
                 "bf16": COLA_PREC_BF16, "bf16x3": COLA_PREC_BF16X3}
 
@@ -46,7 +50,7 @@ class SystemDesc(ctypes.Structure):
 class SolveOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iters", ctypes.c_int32), ("prec", ctypes.c_int32),
                 ("inner_tol", ctypes.c_double), ("max_sweeps", ctypes.c_int32),
-                ("check_every", ctypes.c_int32)]
+                ("check_every", ctypes.c_int32), ("refine", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):

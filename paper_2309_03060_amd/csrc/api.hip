@@ -38,7 +38,7 @@ int32_t alloc_bytes(void** p, size_t bytes) {
 }
 
 void free_ws(Workspace& w) {
-    void* ptrs[] = {w.vx, w.vr, w.vp, w.vq, w.inter[0], w.inter[1], w.r64, w.partials,
+    void* ptrs[] = {w.vx, w.vr, w.vp, w.vq, w.inter[0], w.inter[1], w.r64, w.x64, w.b64, w.partials,
                     w.counters, w.cg, w.outer, w.cnt};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
@@ -74,6 +74,8 @@ int32_t ensure_ws(cola_op_s* op, int nrhs, hipStream_t st) {
     rc |= alloc_bytes(&w.inter[0], vec * op->Jmax);
     rc |= alloc_bytes(&w.inter[1], vec * op->Jmax);
     rc |= alloc_bytes((void**)&w.r64, vec);
+    rc |= alloc_bytes((void**)&w.x64, vec);
+    rc |= alloc_bytes((void**)&w.b64, vec);
     w.part_stride = max_blocks_per_rhs(op);
     rc |= alloc_bytes((void**)&w.partials, sizeof(double) * (size_t)nrhs * w.part_stride);
     rc |= alloc_bytes((void**)&w.counters, sizeof(uint32_t) * (size_t)nrhs);
@@ -163,8 +165,9 @@ int32_t enqueue_mvm(cola_op_s* op, const SysInfo& s, int prec, int nrhs, const v
         sa.K3 = (const char*)fac + (size_t)s.fac_off[2] * fb;
         sa.k2_tstride = s.dims[1] * s.dims[1];
         sa.k3_tstride = s.dims[2] * s.dims[2];
+        sa.gate = tmpl.gate;
+        sa.gate_stride = tmpl.gate_stride;
         sa.cg = tmpl.cg;
-        sa.outer = tmpl.outer;
         {
             ProfScope ps(op->prof, "slab23", st);
             HIP_TRY(launch_slab23(prec, sa, st));
@@ -254,6 +257,8 @@ int32_t enqueue_iteration(cola_op_s* op, const SysInfo& s, int prec, int nrhs, T
     Workspace& w = op->ws;
     PassArgs a = base_args(op);
     a.cg = w.cg;
+    a.gate = &w.cg->active;
+    a.gate_stride = (int32_t)(sizeof(CgState) / sizeof(int32_t));
     a.epi = EPI_CG;
     a.Ep = p;
     a.Er = r;
@@ -262,6 +267,37 @@ int32_t enqueue_iteration(cola_op_s* op, const SysInfo& s, int prec, int nrhs, T
     if (rc != COLA_OK) return rc;
     ProfScope ps(op->prof, "update", st);
     HIP_TRY(cg_update<T>(x, r, p, q, s.n, nrhs, w.cg, w.partials, (int)w.part_stride, w.counters, w.cnt, st));
+    return COLA_OK;
+}
+
+// Reliable-update step appended to every chunk of a mixed-precision solve:
+// for the right-hand sides that asked for it, fold x_lo into the FP64 x,
+// form the FP64 residual b - A x (FP64 factors), and replace r_lo by it.
+struct ReliableTail {
+    double* X;        // FP64 solution (caller's buffer)
+    const double* B;  // FP64 right-hand sides
+    float* xl;        // low-precision iterate
+    float* rl;        // low-precision residual
+};
+
+int32_t enqueue_tail(cola_op_s* op, const SysInfo& s, int nrhs, const ReliableTail& t, bool all_rhs,
+                     hipStream_t st) {
+    Workspace& w = op->ws;
+    HIP_TRY(reliable_fold<float>(t.X, t.xl, s.n, nrhs, w.cg, all_rhs, st));
+    PassArgs a = base_args(op);
+    a.cg = w.cg;
+    if (!all_rhs) {
+        a.gate = &w.cg->need_update;
+        a.gate_stride = (int32_t)(sizeof(CgState) / sizeof(int32_t));
+    }
+    a.epi = EPI_RESID_CG;
+    a.Ep = t.X;
+    a.Er = t.B;
+    int32_t rc = enqueue_mvm(op, s, COLA_PREC_FP64, nrhs, t.X, nullptr, w.r64, a, st);
+    if (rc != COLA_OK) return rc;
+    if (!all_rhs)
+        HIP_TRY(reliable_apply<float>(w.r64, t.rl, s.n, nrhs, w.cg, w.partials, (int)w.part_stride, w.counters,
+                                      w.cnt, st));
     return COLA_OK;
 }
 
@@ -283,13 +319,14 @@ void destroy_graphs(cola_op_s* op) {
 // capture stream; nothing executes during capture).
 template <typename T>
 int32_t capture_chunk(cola_op_s* op, const SysInfo& s, int prec, int nrhs, T* x, T* r, T* p, T* q, int chunk,
-                      ChunkGraph* out) {
+                      const ReliableTail* tail, ChunkGraph* out) {
     if (!op->cap_stream && hipStreamCreateWithFlags(&op->cap_stream, hipStreamNonBlocking) != hipSuccess)
         return COLA_ERR_HIP;
     if (hipStreamBeginCapture(op->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return COLA_ERR_HIP;
     if (op->prof.enabled) op->prof.capture_list = &out->ev;
     int32_t rc = COLA_OK;
     for (int i = 0; i < chunk && rc == COLA_OK; ++i) rc = enqueue_iteration<T>(op, s, prec, nrhs, x, r, p, q, op->cap_stream);
+    if (rc == COLA_OK && tail) rc = enqueue_tail(op, s, nrhs, *tail, false, op->cap_stream);
     op->prof.capture_list = nullptr;
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(op->cap_stream, &g);
@@ -317,25 +354,36 @@ int32_t capture_chunk(cola_op_s* op, const SysInfo& s, int prec, int nrhs, T* x,
 // once on the device.
 template <typename T>
 int32_t run_cg(cola_op_s* op, const SysInfo& s, int prec, int nrhs, T* x, T* r, T* p, T* q, int max_iters,
-               int check_every, hipStream_t st) {
+               int check_every, const ReliableTail* tail, hipStream_t st) {
     Workspace& w = op->ws;
-    if (check_every <= 0) {
-        for (int it = 0; it < max_iters; ++it) {
+    const int chunk = check_every > 0 ? std::min(check_every, max_iters) : (tail ? std::min(32, max_iters) : max_iters);
+    const int nchunks = (max_iters + chunk - 1) / chunk;
+    auto direct_chunk = [&]() -> int32_t {
+        for (int it = 0; it < chunk; ++it) {
             int32_t rc = enqueue_iteration<T>(op, s, prec, nrhs, x, r, p, q, st);
+            if (rc != COLA_OK) return rc;
+        }
+        if (tail) return enqueue_tail(op, s, nrhs, *tail, false, st);
+        return COLA_OK;
+    };
+    if (check_every <= 0) {
+        for (int c = 0; c < nchunks; ++c) {
+            int32_t rc = direct_chunk();
             if (rc != COLA_OK) return rc;
         }
         return COLA_OK;
     }
-    const int chunk = std::min(check_every, max_iters);
     GraphSet* gs = nullptr;
     if (op->graphs_ok) {
-        GraphKey key{&s, prec, nrhs, x, r, p, q, chunk, op->prof.enabled ? 1 : 0, op->tiles_version};
+        GraphKey key{&s, prec, nrhs, x, r, p, q, chunk, (op->prof.enabled ? 1 : 0) + (tail ? 2 : 0),
+                     op->tiles_version};
         auto it = op->graphs.find(key);
+        if (it == op->graphs.end() && op->graphs.size() >= 32) destroy_graphs(op);   // keep the cache bounded
         if (it == op->graphs.end()) {
             GraphSet set;
             int32_t rc = COLA_OK;
             for (int b = 0; b < 2 && rc == COLA_OK; ++b) {
-                rc = capture_chunk<T>(op, s, prec, nrhs, x, r, p, q, chunk, &set.g[b]);
+                rc = capture_chunk<T>(op, s, prec, nrhs, x, r, p, q, chunk, tail, &set.g[b]);
                 if (rc == COLA_OK && hipEventCreateWithFlags(&set.done[b], hipEventDisableTiming) != hipSuccess)
                     rc = COLA_ERR_HIP;
             }
@@ -355,16 +403,15 @@ int32_t run_cg(cola_op_s* op, const SysInfo& s, int prec, int nrhs, T* x, T* r, 
         }
         if (it != op->graphs.end()) gs = &it->second;
     }
-    const int nchunks = (max_iters + chunk - 1) / chunk;
     if (!gs) {
-        for (int it = 0; it < nchunks * chunk; ++it) {
-            if (it > 0 && it % chunk == 0) {
+        for (int c = 0; c < nchunks; ++c) {
+            if (c > 0) {
                 int32_t active = 0;
                 int32_t rc = poll_flag(op, &w.cnt->num_active, st, &active);
                 if (rc != COLA_OK) return rc;
                 if (active <= 0) break;
             }
-            int32_t rc = enqueue_iteration<T>(op, s, prec, nrhs, x, r, p, q, st);
+            int32_t rc = direct_chunk();
             if (rc != COLA_OK) return rc;
         }
         return COLA_OK;
@@ -400,23 +447,49 @@ int32_t solve_system(cola_op_s* op, const SysInfo& s, const double* B, double* X
         double* r = (double*)w.vr;
         double* p = (double*)w.vp;
         double* q = (double*)w.vq;
-        HIP_TRY(cg_prepare<double>(B, r, X, p, n, nrhs, nullptr, w.cg, o->tol, o->max_iters, w.partials, ps,
+        double* x = (double*)w.vx;     // workspace iterate: captured graphs never hold caller pointers
+        HIP_TRY(cg_prepare<double>(B, r, x, p, n, nrhs, nullptr, w.cg, o->tol, o->max_iters, 0.0, w.partials, ps,
                                    w.counters, w.cnt, st));
-        int32_t rc = run_cg<double>(op, s, COLA_PREC_FP64, nrhs, X, r, p, q, o->max_iters, o->check_every, st);
+        int32_t rc = run_cg<double>(op, s, COLA_PREC_FP64, nrhs, x, r, p, q, o->max_iters, o->check_every, nullptr,
+                                    st);
         if (rc != COLA_OK) return rc;
+        HIP_TRY(copy_f64(x, X, (int64_t)nrhs * n, st));
         if (info) HIP_TRY(write_info(info, nullptr, w.cg, nrhs, st));
         return COLA_OK;
     }
-    // iterative refinement: FP64 residual, working-precision inner CG
-    HIP_TRY(fill_i32(&w.cnt->num_outer_active, 0, 1, st));
-    HIP_TRY(outer_init(B, X, n, nrhs, w.outer, o->tol, o->max_sweeps, w.partials, ps, w.counters, w.cnt, st));
     float* xl = (float*)w.vx;
     float* rl = (float*)w.vr;
     float* pl = (float*)w.vp;
     float* ql = (float*)w.vq;
+    if (o->refine == COLA_REFINE_RELIABLE) {
+        // one low-precision CG whose residual is replaced by the FP64 true
+        // residual whenever it has dropped by inner_tol (reliable updates)
+        // the FP64 solution and right-hand side live in the workspace so the
+        // captured chunk graphs never hold caller pointers
+        HIP_TRY(fill_f64(w.x64, 0.0, (int64_t)nrhs * n, st));
+        HIP_TRY(copy_f64(B, w.b64, (int64_t)nrhs * n, st));
+        HIP_TRY(fill_i32(&w.cnt->num_active, 0, 1, st));
+        // plain BF16 operands: restart the direction at each update (signalled by a negative delta)
+        const double delta = (op->prec == COLA_PREC_BF16) ? -o->inner_tol : o->inner_tol;
+        HIP_TRY(cg_prepare<float>(w.b64, rl, xl, pl, n, nrhs, nullptr, w.cg, o->tol, o->max_iters, delta,
+                                  w.partials, ps, w.counters, w.cnt, st));
+        ReliableTail tail{w.x64, w.b64, xl, rl};
+        int32_t rc = run_cg<float>(op, s, op->prec, nrhs, xl, rl, pl, ql, o->max_iters, o->check_every, &tail, st);
+        if (rc != COLA_OK) return rc;
+        rc = enqueue_tail(op, s, nrhs, tail, true, st);       // final fold and true residual for every RHS
+        if (rc != COLA_OK) return rc;
+        HIP_TRY(copy_f64(w.x64, X, (int64_t)nrhs * n, st));
+        if (info) HIP_TRY(write_info(info, nullptr, w.cg, nrhs, st));
+        return COLA_OK;
+    }
+    // restarted iterative refinement: FP64 residual, working-precision inner CG
+    HIP_TRY(fill_i32(&w.cnt->num_outer_active, 0, 1, st));
+    HIP_TRY(outer_init(B, X, n, nrhs, w.outer, o->tol, o->max_sweeps, w.partials, ps, w.counters, w.cnt, st));
     for (int sweep = 0; sweep <= o->max_sweeps; ++sweep) {
         PassArgs a = base_args(op);
         a.outer = w.outer;
+        a.gate = &w.outer->active;
+        a.gate_stride = (int32_t)(sizeof(OuterState) / sizeof(int32_t));
         a.epi = EPI_RESID;
         a.Ep = X;
         a.Er = B;
@@ -430,9 +503,9 @@ int32_t solve_system(cola_op_s* op, const SysInfo& s, const double* B, double* X
             if (active <= 0) break;
         }
         HIP_TRY(fill_i32(&w.cnt->num_active, 0, 1, st));
-        HIP_TRY(cg_prepare<float>(w.r64, rl, xl, pl, n, nrhs, w.outer, w.cg, o->inner_tol, o->max_iters,
+        HIP_TRY(cg_prepare<float>(w.r64, rl, xl, pl, n, nrhs, w.outer, w.cg, o->inner_tol, o->max_iters, 0.0,
                                   w.partials, ps, w.counters, w.cnt, st));
-        rc = run_cg<float>(op, s, op->prec, nrhs, xl, rl, pl, ql, o->max_iters, o->check_every, st);
+        rc = run_cg<float>(op, s, op->prec, nrhs, xl, rl, pl, ql, o->max_iters, o->check_every, nullptr, st);
         if (rc != COLA_OK) return rc;
         HIP_TRY(refine_accumulate<float>(X, xl, n, nrhs, w.outer, st));
         HIP_TRY(outer_bookkeep(w.outer, w.cg, nrhs, w.cnt, st));
@@ -448,7 +521,9 @@ int32_t check_opts(const cola_op_s* op, const cola_solve_opts* o) {
     if (!finite_pos(o->tol) || o->max_iters < 1 || o->check_every < 0) return COLA_ERR_INVALID_ARG;
     if (o->prec != COLA_PREC_FP64) {
         if (o->prec != op->prec) return COLA_ERR_INVALID_ARG;
-        if (!finite_pos(o->inner_tol) || o->max_sweeps < 1) return COLA_ERR_INVALID_ARG;
+        if (!finite_pos(o->inner_tol) || o->inner_tol >= 1.0) return COLA_ERR_INVALID_ARG;
+        if (o->refine != COLA_REFINE_RELIABLE && o->refine != COLA_REFINE_RESTART) return COLA_ERR_INVALID_ARG;
+        if (o->refine == COLA_REFINE_RESTART && o->max_sweeps < 1) return COLA_ERR_INVALID_ARG;
     }
     return COLA_OK;
 }

@@ -24,10 +24,17 @@ struct CgState {
     double beta;       // rho_new / rho_old; 0 before the first direction
     double tol2;       // (tol * ||b||)^2 - stop when rho <= tol2
     double bnorm2;     // ||b||^2 of this solve's right-hand side
+    double delta;      // reliable updates: replace r once ||r|| < delta * rmax (0: off)
+    double rmax;       // ||r|| at the last reliable update
+    double rho_true;   // ||b - A x||^2 from the latest FP64 residual
     int32_t active;    // 1 while iterating
     int32_t iters;
     int32_t status;    // COLA_* numerical status of this solve
     int32_t max_iters;
+    int32_t need_update; // reliable update requested for the end of this chunk
+    int32_t fails;     // consecutive reliable updates after which the true residual missed tol
+    int32_t updates;   // reliable updates done
+    int32_t restart_dir; // reliable updates restart the direction (p = r) instead of keeping it
 };
 
 // Refinement (outer) state, one per RHS.

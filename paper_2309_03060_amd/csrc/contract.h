@@ -9,6 +9,7 @@ enum Epilogue : int32_t {
     EPI_CG     = 1,   // p = r + beta p_old (written back), q = contraction + diag * p, mu partial p.q
     EPI_RESID  = 2,   // r = b - (contraction + diag * x), partial r.r
     EPI_MATVEC = 3,   // y = contraction + diag * x
+    EPI_RESID_CG = 4, // as EPI_RESID, total ||r||^2 goes to CgState::rho_true (reliable updates)
 };
 
 // One pass contracts a single tensor mode with one factor per Kronecker term.
@@ -40,8 +41,9 @@ struct PassArgs {
 
     double* partials; int32_t part_stride;   // per right-hand side
     uint32_t* counters;                       // per right-hand side
-    CgState* cg;                              // CG gate / scalars (null: no gating)
-    OuterState* outer;                        // refinement gate / residual finalize
+    const int32_t* gate; int32_t gate_stride; // per-RHS flag (int32 stride); null: no gating
+    CgState* cg;                              // CG scalars (beta, alpha, finalize)
+    OuterState* outer;                        // refinement residual finalize
     SolveCounters* cnt;
 };
 

@@ -74,9 +74,7 @@ __device__ inline void split_value(typename P::V v, typename P::L* out) {
 }
 
 __device__ inline bool gate_of(const PassArgs& a, int64_t rhs) {
-    if (a.cg) return a.cg[rhs].active != 0;
-    if (a.outer) return a.outer[rhs].active != 0;
-    return true;
+    return a.gate ? a.gate[rhs * a.gate_stride] != 0 : true;
 }
 
 // 4 consecutive elements (the address is a multiple of 4 elements).
@@ -130,7 +128,7 @@ __global__ __launch_bounds__(kThreads) void k_contract(PassArgs a) {
         m0 = (int64_t)blockIdx.x * MT;
         n0 = (int64_t)(blockIdx.y % nNt) * NT;
         tout = blockIdx.y / nNt;
-        if (a.cg || a.outer) {
+        if (a.gate) {
             const int64_t last = (m0 + MT < a.G ? m0 + MT : a.G) - 1;
             bool any = false;
             for (int64_t r = m0 / a.a_per_rhs; r <= last / a.a_per_rhs; ++r) any |= gate_of(a, r);
@@ -372,7 +370,7 @@ __global__ __launch_bounds__(kThreads) void k_contract(PassArgs a) {
                         for (int c = 0; c < cnt; ++c) dot += (double)pn[c] * (double)out[c];
                         if (full) { store4(Y + idx, out); store4((V*)a.Epout + idx, pn); }
                         else for (int c = 0; c < cnt; ++c) { Y[idx + c] = out[c]; ((V*)a.Epout)[idx + c] = pn[c]; }
-                    } else if (a.epi == EPI_RESID) {
+                    } else if (a.epi == EPI_RESID || a.epi == EPI_RESID_CG) {
 #pragma unroll
                         for (int c = 0; c < 4; ++c) out[c] = w4[c] - (val[c] + dg[c] * u[c]);
                         for (int c = 0; c < cnt; ++c) dot += (double)out[c] * (double)out[c];
@@ -391,7 +389,7 @@ __global__ __launch_bounds__(kThreads) void k_contract(PassArgs a) {
     }
 
     if constexpr (!ROWS) {
-        if (a.epi == EPI_CG || a.epi == EPI_RESID) {
+        if (a.epi == EPI_CG || a.epi == EPI_RESID || a.epi == EPI_RESID_CG) {
             const double s = block_sum(dot, red);
             const int64_t nblk = nBt * nMt;
             const int64_t myb = (blockIdx.x % nBt) + nBt * (blockIdx.y % nMt);
@@ -407,6 +405,8 @@ __global__ __launch_bounds__(kThreads) void k_contract(PassArgs a) {
                     } else {
                         st.alpha = st.rho / tot;
                     }
+                } else if (a.epi == EPI_RESID_CG) {
+                    a.cg[g].rho_true = tot;
                 } else {
                     OuterState& o = a.outer[g];
                     const double rn = sqrt(tot);

@@ -32,6 +32,8 @@ struct Workspace {
     void* vx = nullptr; void* vr = nullptr; void* vp = nullptr; void* vq = nullptr;  // CG vectors (8 B / elem)
     void* inter[2] = {nullptr, nullptr};                                             // MVM intermediates
     double* r64 = nullptr;                                                            // FP64 residual
+    double* x64 = nullptr;                                                            // FP64 solution
+    double* b64 = nullptr;                                                            // FP64 right-hand sides
     double* partials = nullptr;
     uint32_t* counters = nullptr;
     CgState* cg = nullptr;

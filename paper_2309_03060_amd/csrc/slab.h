@@ -14,8 +14,8 @@ struct SlabArgs {
     const void* R;
     void* Y; int64_t y_tstride;
     const void* K2; const void* K3; int64_t k2_tstride, k3_tstride;
-    CgState* cg;
-    OuterState* outer;
+    const int32_t* gate; int32_t gate_stride;   // per-RHS flag; null: no gating
+    CgState* cg;                                // beta of the direction update
 };
 
 bool slab_supported(int prec, int64_t n2, int64_t n3);

@@ -66,8 +66,7 @@ __global__ __launch_bounds__(kThreads) void k_slab23(SlabArgs a) {
 
     for (int64_t sl = blockIdx.x; sl < a.nslabs; sl += gridDim.x) {
         const int64_t rhs = sl / a.a_per_rhs;
-        if (a.cg && !a.cg[rhs].active) continue;
-        if (a.outer && !a.outer[rhs].active) continue;
+        if (a.gate && !a.gate[rhs * a.gate_stride]) continue;
         const double be = a.pnew ? a.cg[rhs].beta : 0.0;
         const int64_t base = sl * slab;
         __syncthreads();                     // previous slab's LDS reads are done

@@ -9,6 +9,7 @@ int vec_blocks_per_rhs(int64_t n);
 hipError_t fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
 hipError_t fill_f64(double* p, double v, int64_t n, hipStream_t s);
 hipError_t fill_f32(float* p, float v, int64_t n, hipStream_t s);
+hipError_t copy_f64(const double* in, double* out, int64_t n, hipStream_t s);
 
 hipError_t outer_init(const double* B, double* X, int64_t n, int nrhs, OuterState* outer, double tol,
                       int max_sweeps, double* partials, int part_stride, uint32_t* counters,
@@ -16,8 +17,15 @@ hipError_t outer_init(const double* B, double* X, int64_t n, int nrhs, OuterStat
 
 template <typename T>
 hipError_t cg_prepare(const double* src, T* r, T* x, T* p, int64_t n, int nrhs, const OuterState* outer,
-                      CgState* cg, double tol, int max_iters, double* partials, int part_stride,
+                      CgState* cg, double tol, int max_iters, double delta, double* partials, int part_stride,
                       uint32_t* counters, SolveCounters* cnt, hipStream_t s);
+
+template <typename T>
+hipError_t reliable_fold(double* x64, T* xlo, int64_t n, int nrhs, const CgState* cg, bool all_rhs, hipStream_t s);
+
+template <typename T>
+hipError_t reliable_apply(const double* r64, T* rlo, int64_t n, int nrhs, CgState* cg, double* partials,
+                          int part_stride, uint32_t* counters, SolveCounters* cnt, hipStream_t s);
 
 template <typename T>
 hipError_t cg_update(T* x, T* r, const T* p, const T* q, int64_t n, int nrhs, CgState* cg, double* partials,

@@ -31,6 +31,11 @@ __global__ void k_fill(T* p, T v, int64_t n) {
         p[i] = v;
 }
 
+__global__ void k_copy_f64(const double* in, double* out, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = in[i];
+}
+
 // ---------------------------------------------------------------------------
 // Refinement setup: ||b||^2 per RHS, x = 0, refinement state.
 __global__ __launch_bounds__(kThreads) void k_outer_init(const double* B, double* X, int64_t n,
@@ -79,8 +84,8 @@ __global__ __launch_bounds__(kThreads) void k_outer_init(const double* B, double
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_cg_prepare(const double* src, T* r, T* x, T* p, int64_t n,
                                                          const OuterState* outer, CgState* cg, double tol,
-                                                         int max_iters, double* partials, int part_stride,
-                                                         uint32_t* counters, SolveCounters* cnt) {
+                                                         int max_iters, double delta, double* partials,
+                                                         int part_stride, uint32_t* counters, SolveCounters* cnt) {
     __shared__ double red[4];
     const int64_t g = blockIdx.y;
     if (outer && !outer[g].active) {
@@ -116,6 +121,13 @@ __global__ __launch_bounds__(kThreads) void k_cg_prepare(const double* src, T* r
         st.beta = 0.0;
         st.iters = 0;
         st.max_iters = max_iters;
+        st.delta = delta < 0.0 ? -delta : delta;
+        st.restart_dir = delta < 0.0;          // a negative delta asks for direction restarts
+        st.rmax = sqrt(tot);
+        st.rho_true = tot;
+        st.need_update = 0;
+        st.fails = 0;
+        st.updates = 0;
         if (!finite_d(tot)) {
             st.status = COLA_ERR_NONFINITE;
             st.active = 0;
@@ -175,10 +187,19 @@ __global__ __launch_bounds__(kThreads) void k_cg_update(T* x, T* r, const T* p, 
         CgState& st = cg[g];
         st.iters += 1;
         bool stop = true;
-        if (!finite_d(tot)) st.status = COLA_ERR_NONFINITE;
-        else if (tot <= st.tol2) st.status = COLA_OK;
-        else if (st.iters >= st.max_iters) st.status = COLA_NOT_CONVERGED;
-        else stop = false;
+        if (!finite_d(tot)) {
+            st.status = COLA_ERR_NONFINITE;
+        } else if (tot <= st.tol2) {
+            // plain CG: converged.  Reliable updates: pause and let the FP64
+            // residual at the end of the chunk decide.
+            if (st.delta > 0.0) st.need_update = 1;
+            else st.status = COLA_OK;
+        } else if (st.iters >= st.max_iters) {
+            st.status = COLA_NOT_CONVERGED;
+        } else {
+            stop = false;
+            if (st.delta > 0.0 && tot < st.delta * st.delta * st.rmax * st.rmax) st.need_update = 1;
+        }
         st.beta = tot / st.rho;
         st.rho = tot;
         if (stop) {
@@ -219,6 +240,73 @@ __global__ void k_outer_bookkeep(OuterState* outer, const CgState* cg, int nrhs,
     }
 }
 
+// Reliable update, step 1 (gated on need_update, or every RHS when
+// all_rhs): fold the low-precision iterate into the FP64 solution, x_lo = 0.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_reliable_fold(double* x64, T* xlo, int64_t n, const CgState* cg,
+                                                            int all_rhs) {
+    const int64_t g = blockIdx.y;
+    if (!all_rhs && !cg[g].need_update) return;
+    double* xg = x64 + g * n;
+    T* lg = xlo + g * n;
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
+        xg[i] += (double)lg[i];
+        lg[i] = (T)0;
+    }
+}
+
+// Reliable update, step 3 (after the FP64 residual r64 = b - A x64 and its
+// norm rho_true): r_lo = r64; the last block decides convergence from the
+// true residual, resumes a paused RHS, and rescales beta so the next
+// direction is r_new + (rho_true / rho_old) p.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_reliable_apply(const double* r64, T* rlo, int64_t n, CgState* cg,
+                                                             double* partials, int part_stride, uint32_t* counters,
+                                                             SolveCounters* cnt) {
+    __shared__ double red[4];
+    const int64_t g = blockIdx.y;
+    if (!cg[g].need_update) return;
+    const double* rg = r64 + g * n;
+    T* lg = rlo + g * n;
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads)
+        lg[i] = (T)rg[i];
+    double tot;
+    if (last_block_reduce(0.0, partials + g * part_stride, counters + g, gridDim.x, blockIdx.x, &tot, red) &&
+        threadIdx.x == 0) {
+        CgState& st = cg[g];
+        const double rt = st.rho_true;
+        const bool was_active = st.active != 0;
+        st.need_update = 0;
+        st.updates += 1;
+        bool run = false;
+        if (!finite_d(rt)) {
+            st.status = COLA_ERR_NONFINITE;
+        } else if (rt <= st.tol2) {
+            st.status = COLA_OK;
+        } else {
+            if (!was_active) st.fails += 1;       // recursive residual converged, true one did not
+            else st.fails = 0;
+            if (st.fails >= 3) st.status = COLA_STAGNATED;
+            else if (st.iters >= st.max_iters) st.status = COLA_NOT_CONVERGED;
+            else run = true;
+            // keep the search direction (beta rescaled to the replaced residual)
+            // unless the working precision is too coarse for the old direction
+            // to stay useful
+            if (st.restart_dir) st.beta = 0.0;
+            else if (st.rho > 0.0) st.beta = rt * st.beta / st.rho;
+            st.rho = rt;
+            st.rmax = sqrt(rt);
+        }
+        if (run && !was_active) {
+            st.active = 1;
+            atomicAdd(&cnt->num_active, 1);
+        } else if (!run && was_active) {
+            st.active = 0;
+            atomicSub(&cnt->num_active, 1);
+        }
+    }
+}
+
 // Public per-RHS outcome.
 __global__ void k_write_info(cola_solve_info* info, const OuterState* outer, const CgState* cg, int nrhs) {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
@@ -229,6 +317,13 @@ __global__ void k_write_info(cola_solve_info* info, const OuterState* outer, con
         o.iters = outer[g].iters;
         o.sweeps = outer[g].sweeps;
         o.relres = outer[g].relres;
+    } else if (cg[g].delta > 0.0) {             // reliable updates: report the true residual
+        o.status = cg[g].status;
+        o.iters = cg[g].iters;
+        o.sweeps = cg[g].updates;
+        o.relres = cg[g].bnorm2 > 0.0 ? sqrt(cg[g].rho_true / cg[g].bnorm2) : sqrt(cg[g].rho_true);
+        if (o.status == COLA_NOT_CONVERGED && cg[g].bnorm2 > 0.0 && cg[g].rho_true <= cg[g].tol2)
+            o.status = COLA_OK;
     } else {
         o.status = cg[g].status;
         o.iters = cg[g].iters;
@@ -282,6 +377,10 @@ hipError_t fill_f64(double* p, double v, int64_t n, hipStream_t s) {
     hipLaunchKernelGGL(k_fill<double>, dim3(grid_for(n, 256 * 8, 65536)), dim3(256), 0, s, p, v, n);
     return hipGetLastError();
 }
+hipError_t copy_f64(const double* in, double* out, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_copy_f64, dim3(grid_for(n, 256 * 8, 65536)), dim3(256), 0, s, in, out, n);
+    return hipGetLastError();
+}
 hipError_t fill_f32(float* p, float v, int64_t n, hipStream_t s) {
     hipLaunchKernelGGL(k_fill<float>, dim3(grid_for(n, 256 * 8, 65536)), dim3(256), 0, s, p, v, n);
     return hipGetLastError();
@@ -298,17 +397,38 @@ hipError_t outer_init(const double* B, double* X, int64_t n, int nrhs, OuterStat
 
 template <typename T>
 hipError_t cg_prepare(const double* src, T* r, T* x, T* p, int64_t n, int nrhs, const OuterState* outer,
-                      CgState* cg, double tol, int max_iters, double* partials, int part_stride,
+                      CgState* cg, double tol, int max_iters, double delta, double* partials, int part_stride,
                       uint32_t* counters, SolveCounters* cnt, hipStream_t s) {
     dim3 grid(vec_blocks_per_rhs(n), nrhs);
     hipLaunchKernelGGL(k_cg_prepare<T>, grid, dim3(kThreads), 0, s, src, r, x, p, n, outer, cg, tol,
-                       max_iters, partials, part_stride, counters, cnt);
+                       max_iters, delta, partials, part_stride, counters, cnt);
     return hipGetLastError();
 }
 template hipError_t cg_prepare<float>(const double*, float*, float*, float*, int64_t, int, const OuterState*,
-                                      CgState*, double, int, double*, int, uint32_t*, SolveCounters*, hipStream_t);
+                                      CgState*, double, int, double, double*, int, uint32_t*, SolveCounters*,
+                                      hipStream_t);
 template hipError_t cg_prepare<double>(const double*, double*, double*, double*, int64_t, int, const OuterState*,
-                                       CgState*, double, int, double*, int, uint32_t*, SolveCounters*, hipStream_t);
+                                       CgState*, double, int, double, double*, int, uint32_t*, SolveCounters*,
+                                       hipStream_t);
+
+template <typename T>
+hipError_t reliable_fold(double* x64, T* xlo, int64_t n, int nrhs, const CgState* cg, bool all_rhs, hipStream_t s) {
+    dim3 grid(vec_blocks_per_rhs(n), nrhs);
+    hipLaunchKernelGGL(k_reliable_fold<T>, grid, dim3(kThreads), 0, s, x64, xlo, n, cg, all_rhs ? 1 : 0);
+    return hipGetLastError();
+}
+template hipError_t reliable_fold<float>(double*, float*, int64_t, int, const CgState*, bool, hipStream_t);
+
+template <typename T>
+hipError_t reliable_apply(const double* r64, T* rlo, int64_t n, int nrhs, CgState* cg, double* partials,
+                          int part_stride, uint32_t* counters, SolveCounters* cnt, hipStream_t s) {
+    dim3 grid(vec_blocks_per_rhs(n), nrhs);
+    hipLaunchKernelGGL(k_reliable_apply<T>, grid, dim3(kThreads), 0, s, r64, rlo, n, cg, partials, part_stride,
+                       counters, cnt);
+    return hipGetLastError();
+}
+template hipError_t reliable_apply<float>(const double*, float*, int64_t, int, CgState*, double*, int, uint32_t*,
+                                          SolveCounters*, hipStream_t);
 
 template <typename T>
 hipError_t cg_update(T* x, T* r, const T* p, const T* q, int64_t n, int nrhs, CgState* cg, double* partials,

@@ -119,8 +119,9 @@ class KronOperator:
                                                               dtype, p, _stream_ptr()))
         return Y
 
-    def _opts(self, tol, max_iters, prec, inner_tol, max_sweeps, check_every) -> L.SolveOpts:
+    def _opts(self, tol, max_iters, prec, inner_tol, max_sweeps, check_every, refine="reliable") -> L.SolveOpts:
         o = L.SolveOpts()
+        o.refine = L.REFINE_BY_NAME[refine]
         o.tol = float(tol)
         o.max_iters = int(max_iters)
         o.prec = self.prec if prec is None else L.PREC_BY_NAME[prec]
@@ -130,23 +131,23 @@ class KronOperator:
         return o
 
     def solve(self, B: torch.Tensor, nrhs: int, tol: float = 1e-6, max_iters: int = 10000,
-              prec: Optional[str] = None, inner_tol: float = 1e-4, max_sweeps: int = 20,
-              check_every: int = 32, info: Optional[torch.Tensor] = None):
+              prec: Optional[str] = None, inner_tol: float = 0.1, max_sweeps: int = 20,
+              check_every: int = 32, info: Optional[torch.Tensor] = None, refine: str = "reliable"):
         """X = A^{-1} B (cola_cg_solve); returns (X, info tensor on device)."""
         if B.dtype != torch.float64 or not B.is_contiguous():
             raise ValueError("B must be a contiguous float64 device tensor")
         X = torch.empty_like(B)
         if info is None:
             info = torch.empty(len(self.sizes) * nrhs * 6, dtype=torch.int32, device=B.device)
-        o = self._opts(tol, max_iters, prec, inner_tol, max_sweeps, check_every)
+        o = self._opts(tol, max_iters, prec, inner_tol, max_sweeps, check_every, refine)
         L.check("cola_cg_solve", self.lib.cola_cg_solve(self.handle, B.data_ptr(), X.data_ptr(), nrhs,
                                                         ctypes.byref(o), info.data_ptr(), _stream_ptr()))
         return X, info
 
     def solve_backward(self, X: torch.Tensor, G: torch.Tensor, nrhs: int, tol: float = 1e-6,
-                       max_iters: int = 10000, prec: Optional[str] = None, inner_tol: float = 1e-4,
+                       max_iters: int = 10000, prec: Optional[str] = None, inner_tol: float = 0.1,
                        max_sweeps: int = 20, check_every: int = 32, want_factors: bool = True,
-                       want_diag: bool = True):
+                       want_diag: bool = True, refine: str = "reliable"):
         """Adjoint backward (cola_cg_solve_backward): Lambda, dfactors, ddiag, dsigma2, info."""
         dev = X.device
         Lam = torch.empty_like(X)
@@ -174,7 +175,7 @@ class KronOperator:
                 dptrs.append(None)
         ds2 = torch.empty(len(self.systems), dtype=torch.float64, device=dev)
         info = torch.empty(len(self.sizes) * nrhs * 6, dtype=torch.int32, device=dev)
-        o = self._opts(tol, max_iters, prec, inner_tol, max_sweeps, check_every)
+        o = self._opts(tol, max_iters, prec, inner_tol, max_sweeps, check_every, refine)
         fa = (ctypes.c_void_p * max(1, len(ptrs)))(*ptrs) if want_factors else None
         da = (ctypes.c_void_p * len(dptrs))(*dptrs)
         L.check("cola_cg_solve_backward", self.lib.cola_cg_solve_backward(

@@ -25,7 +25,7 @@ def test_backward_matches_oracle_closed_forms(dims, nterms, diag, prec):
     Lref = direct.cholesky_solve(s.factors, W, s.sigma2, s.diag)
     gref = grad.grad_kron(s.factors, Xref, Lref, diag)
     op = make_op([s], prec="fp32" if prec == "fp64" else prec)
-    kw = dict(tol=1e-11, max_iters=4000, prec=prec, inner_tol=1e-4, max_sweeps=40)
+    kw = dict(tol=1e-11, max_iters=4000, prec=prec)
     X, _ = op.solve(pack([B]), nrhs, **kw)
     Lam, dfac, ddiag, ds2, info = op.solve_backward(X, pack([W]), nrhs, **kw)
     assert _rel(unpack(Lam, [s], nrhs)[0], Lref) <= 1e-8
@@ -73,7 +73,7 @@ def test_autograd_lengthscale_and_sigma2_uneven_batch():
         specs.append(SystemSpec(factors=[facs], sigma2=s2))
     B = torch.cat([torch.tensor(b.reshape(-1), device=dev) for b in w.B]).requires_grad_(True)
     Wt = torch.cat([torch.tensor(x.reshape(-1), device=dev) for x in w.W])
-    X = kron_cg_solve(specs, B, 1, tol=1e-11, max_iters=4000, prec="fp32", inner_tol=1e-4, max_sweeps=40)
+    X = kron_cg_solve(specs, B, 1, tol=1e-11, max_iters=4000, prec="fp32")
     loss = (X * Wt).sum()
     loss.backward()
     li = 0
