@@ -12,6 +12,7 @@
 
 #include "grad.h"
 #include "op.h"
+#include "resident.h"
 #include "slab.h"
 #include "vector.h"
 
@@ -514,6 +515,122 @@ int32_t solve_system(cola_op_s* op, const SysInfo& s, const double* B, double* X
     return COLA_OK;
 }
 
+void free_resident(cola_op_s* op) {
+    void* ptrs[] = {op->res_sys, op->res_order, op->res_x, op->res_r, op->res_p, op->res_t64, op->res_st,
+                    op->res_queue};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    op->res_sys = nullptr;
+    op->res_order = nullptr;
+    op->res_x = op->res_r = op->res_p = nullptr;
+    op->res_t64 = nullptr;
+    op->res_st = nullptr;
+    op->res_queue = nullptr;
+    op->res_nrhs = 0;
+}
+
+int32_t ensure_resident(cola_op_s* op, int nrhs, hipStream_t st) {
+    if (op->res_nrhs >= nrhs && op->res_nrhs == nrhs) return COLA_OK;
+    free_resident(op);
+    const int nsys = (int)op->sys.size();
+    const int64_t nitems = (int64_t)nsys * nrhs;
+    const size_t vec = (size_t)nrhs * op->n_total;
+    int32_t rc = COLA_OK;
+    rc |= alloc_bytes(&op->res_sys, sizeof(ResSys) * nsys);
+    rc |= alloc_bytes((void**)&op->res_order, sizeof(int32_t) * nitems);
+    rc |= alloc_bytes((void**)&op->res_x, sizeof(float) * vec);
+    rc |= alloc_bytes((void**)&op->res_r, sizeof(float) * vec);
+    rc |= alloc_bytes((void**)&op->res_p, sizeof(float) * vec);
+    rc |= alloc_bytes((void**)&op->res_t64, sizeof(double) * vec);
+    rc |= alloc_bytes((void**)&op->res_st, sizeof(CgState) * nitems);
+    rc |= alloc_bytes((void**)&op->res_queue, sizeof(uint32_t) * 4);
+    if (rc != COLA_OK) {
+        free_resident(op);
+        return COLA_ERR_OOM;
+    }
+    std::vector<ResSys> hs(nsys);
+    for (int i = 0; i < nsys; ++i) {
+        const SysInfo& s = op->sys[i];
+        ResSys& r = hs[i];
+        r.n1 = (int32_t)s.dims[0];
+        r.n2 = (int32_t)s.dims[1];
+        r.n = s.n;
+        r.vec_off = s.vec_off;
+        r.k1_off = s.fac_off[0];
+        r.k2_off = s.fac_off[1];
+        r.diag_off = s.diag_off;
+        r.sigma2 = s.sigma2;
+    }
+    // largest systems first: the longest solves start early (LPT order)
+    std::vector<int32_t> order(nitems);
+    for (int64_t i = 0; i < nitems; ++i) order[i] = (int32_t)i;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+        return op->sys[x / nrhs].n > op->sys[y / nrhs].n;
+    });
+    // synchronous uploads: this runs once per (op, nrhs), outside any capture
+    if (hipMemcpy(op->res_sys, hs.data(), sizeof(ResSys) * nsys, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(op->res_order, order.data(), sizeof(int32_t) * nitems, hipMemcpyHostToDevice) != hipSuccess) {
+        free_resident(op);
+        return COLA_ERR_HIP;
+    }
+    HIP_TRY(fill_i32((int32_t*)op->res_st, 0, nitems * (int64_t)sizeof(CgState) / 4, st));
+    op->res_nrhs = nrhs;
+    return COLA_OK;
+}
+
+// All systems at once through the resident kernel: rounds of (persistent FP32
+// CG until each item needs a reliable update) + (FP64 residual of the items
+// that asked), then one FP64 residual of every item for the final report.
+int32_t solve_resident(cola_op_s* op, const double* B, double* X, int nrhs, const cola_solve_opts* o,
+                       cola_solve_info* info, hipStream_t st) {
+    int32_t rc = ensure_ws(op, 1, st);              // counters and pinned poll flag
+    if (rc != COLA_OK) return rc;
+    rc = ensure_resident(op, nrhs, st);
+    if (rc != COLA_OK) return rc;
+    Workspace& w = op->ws;
+    ResArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.sys = (const ResSys*)op->res_sys;
+    a.order = op->res_order;
+    a.nitems = (int32_t)(op->sys.size() * nrhs);
+    a.nrhs = nrhs;
+    a.queue = op->res_queue;
+    a.fac32 = op->fac32;
+    a.fac64 = op->fac64;
+    a.diag32 = op->diag32;
+    a.diag64 = op->diag64;
+    a.x = op->res_x;
+    a.r = op->res_r;
+    a.p = op->res_p;
+    a.x64 = X;
+    a.b64 = B;
+    a.t64 = op->res_t64;
+    a.st = op->res_st;
+    a.cnt = w.cnt;
+    HIP_TRY(fill_i32(&w.cnt->num_active, 0, 1, st));
+    HIP_TRY(launch_resident_prepare(a, o->tol, o->max_iters, o->inner_tol, st));
+    const int grid = std::max(1, std::min(a.nitems, op->num_cus > 0 ? op->num_cus : 256));
+    const int rounds = std::max(o->max_sweeps, 32);
+    for (int rd = 0; rd < rounds; ++rd) {
+        if (o->check_every > 0 && rd > 0) {
+            int32_t active = 0;
+            rc = poll_flag(op, &w.cnt->num_active, st, &active);
+            if (rc != COLA_OK) return rc;
+            if (active <= 0) break;
+        }
+        HIP_TRY(fill_i32((int32_t*)op->res_queue, 0, 1, st));
+        {
+            ProfScope ps(op->prof, "resident", st);
+            HIP_TRY(launch_resident_cg(a, grid, st));
+        }
+        HIP_TRY(launch_resident_resid64(a, st));
+    }
+    a.all_items = 1;
+    HIP_TRY(launch_resident_resid64(a, st));
+    if (info) HIP_TRY(write_info(info, nullptr, op->res_st, a.nitems, st));
+    return COLA_OK;
+}
+
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
 int32_t check_opts(const cola_op_s* op, const cola_solve_opts* o) {
@@ -616,6 +733,11 @@ int32_t cola_op_create(const cola_system_desc* systems, int32_t nsys, int32_t pr
     op->n_total = voff;
     op->fac_elems = fac;
     op->diag_elems = dg;
+    // many small two-mode single-term systems go through the resident batched kernel
+    op->resident_ok = (prec == COLA_PREC_FP32) && nsys >= 2;
+    for (const SysInfo& s : op->sys)
+        if (s.F != 2 || s.J != 1 || s.dims[0] > kResMax || s.dims[1] > kResMax) op->resident_ok = false;
+    (void)hipDeviceGetAttribute(&op->num_cus, hipDeviceAttributeMultiprocessorCount, op->device);
 
     int32_t rc = alloc_bytes((void**)&op->fac64, sizeof(double) * fac);
     if (rc == COLA_OK && dg > 0) rc = alloc_bytes((void**)&op->diag64, sizeof(double) * dg);
@@ -679,6 +801,7 @@ int32_t cola_op_destroy(cola_op_t op) {
     (void)hipDeviceSynchronize();
     destroy_graphs(op);
     if (op->cap_stream) (void)hipStreamDestroy(op->cap_stream);
+    free_resident(op);
     free_ws(op->ws);
     void* ptrs[] = {op->fac64, op->fac32, op->facbf, op->diag64, op->diag32, op->grad_buf};
     for (void* p : ptrs)
@@ -724,6 +847,9 @@ int32_t cola_cg_solve(cola_op_t op, const double* B, double* X, int32_t nrhs, co
     int32_t rc = check_opts(op, opts);
     if (rc != COLA_OK) return rc;
     hipStream_t st = S(stream);
+    if (op->resident_ok && op->use_resident && opts->prec == COLA_PREC_FP32 &&
+        opts->refine == COLA_REFINE_RELIABLE)
+        return solve_resident(op, B, X, nrhs, opts, info, st);
     rc = ensure_ws(op, nrhs, st);
     if (rc != COLA_OK) return rc;
     for (size_t i = 0; i < op->sys.size(); ++i) {

@@ -123,6 +123,42 @@ __device__ inline bool last_block_reduce(double partial, double* partials, uint3
     return true;
 }
 
+// After a reliable update has put ||b - A x||^2 into st.rho_true (x already
+// holds the folded FP64 solution and r the replaced residual): decide
+// convergence from the true residual, resume a paused right-hand side, and
+// rescale beta so the next direction is r_new + (rho_true / rho_old) p (or
+// restart it when the working precision is too coarse for the old one).
+// Runs in one thread per right-hand side.
+__device__ inline void reliable_finish(CgState& st, SolveCounters* cnt) {
+    const double rt = st.rho_true;
+    const bool was_active = st.active != 0;
+    st.need_update = 0;
+    st.updates += 1;
+    bool run = false;
+    if (!__builtin_isfinite(rt)) {
+        st.status = COLA_ERR_NONFINITE;
+    } else if (rt <= st.tol2) {
+        st.status = COLA_OK;
+    } else {
+        if (!was_active) st.fails += 1;       // recursive residual converged, true one did not
+        else st.fails = 0;
+        if (st.fails >= 3) st.status = COLA_STAGNATED;
+        else if (st.iters >= st.max_iters) st.status = COLA_NOT_CONVERGED;
+        else run = true;
+        if (st.restart_dir) st.beta = 0.0;
+        else if (st.rho > 0.0) st.beta = rt * st.beta / st.rho;
+        st.rho = rt;
+        st.rmax = sqrt(rt);
+    }
+    if (run && !was_active) {
+        st.active = 1;
+        atomicAdd(&cnt->num_active, 1);
+    } else if (!run && was_active) {
+        st.active = 0;
+        atomicSub(&cnt->num_active, 1);
+    }
+}
+
 // Row (within a 16x16 tile) of accumulator element v held by `lane`.  The
 // column is always lane % 16.  FP32/BF16 16x16 MFMAs give each lane four
 // consecutive rows; the FP64 16x16x4 MFMA interleaves them by 4.

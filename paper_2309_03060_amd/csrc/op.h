@@ -119,6 +119,17 @@ struct cola_op_s {
     int tiles_version = 0;          // bumped when the tile table changes (invalidates graphs)
     bool graphs_ok = true;          // false after a capture failure: launch directly
     bool use_slab = true;           // fuse modes 2 and 3 of three-mode terms when slabs fit in LDS
+    bool resident_ok = false;       // every system fits the resident batched kernel
+    bool use_resident = true;
+    int num_cus = 0;
+    // resident-path workspace (allocated for res_nrhs right-hand sides)
+    int res_nrhs = 0;
+    void* res_sys = nullptr;        // ResSys[nsys]
+    int32_t* res_order = nullptr;   // nsys * nrhs items, largest systems first
+    float* res_x = nullptr; float* res_r = nullptr; float* res_p = nullptr;
+    double* res_t64 = nullptr;
+    cola::CgState* res_st = nullptr;
+    uint32_t* res_queue = nullptr;
     hipStream_t cap_stream = nullptr;
     std::map<cola::GraphKey, cola::GraphSet> graphs;
 };

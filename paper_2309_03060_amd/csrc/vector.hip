@@ -273,37 +273,7 @@ __global__ __launch_bounds__(kThreads) void k_reliable_apply(const double* r64, 
     double tot;
     if (last_block_reduce(0.0, partials + g * part_stride, counters + g, gridDim.x, blockIdx.x, &tot, red) &&
         threadIdx.x == 0) {
-        CgState& st = cg[g];
-        const double rt = st.rho_true;
-        const bool was_active = st.active != 0;
-        st.need_update = 0;
-        st.updates += 1;
-        bool run = false;
-        if (!finite_d(rt)) {
-            st.status = COLA_ERR_NONFINITE;
-        } else if (rt <= st.tol2) {
-            st.status = COLA_OK;
-        } else {
-            if (!was_active) st.fails += 1;       // recursive residual converged, true one did not
-            else st.fails = 0;
-            if (st.fails >= 3) st.status = COLA_STAGNATED;
-            else if (st.iters >= st.max_iters) st.status = COLA_NOT_CONVERGED;
-            else run = true;
-            // keep the search direction (beta rescaled to the replaced residual)
-            // unless the working precision is too coarse for the old direction
-            // to stay useful
-            if (st.restart_dir) st.beta = 0.0;
-            else if (st.rho > 0.0) st.beta = rt * st.beta / st.rho;
-            st.rho = rt;
-            st.rmax = sqrt(rt);
-        }
-        if (run && !was_active) {
-            st.active = 1;
-            atomicAdd(&cnt->num_active, 1);
-        } else if (!run && was_active) {
-            st.active = 0;
-            atomicSub(&cnt->num_active, 1);
-        }
+        reliable_finish(cg[g], cnt);
     }
 }
 
