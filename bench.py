@@ -59,6 +59,10 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tts", action="store_true", help="skip the mixed-vs-FP64 time-to-solution runs")
     ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"],
+                    help="c2 (default): 64^3 x 32 RHS; c3: 256 uneven systems with backward; c4: 256^3 x 8 RHS; "
+                         "c5: sum of 4 1024^2 terms + diag with backward; c1: 64^2 FP64")
+    ap.add_argument("--prec", default=None, help="working precision for c4/c5 (fp32, bf16x3, bf16)")
     return ap.parse_args()
 
 
@@ -84,11 +88,199 @@ def cpu_baseline(w, iters):
                       f"({rhs_iters} RHS*iters) in {dt:.2f} s"}
 
 
+def kernel_table(op, names):
+    kern = {}
+    for name in names:
+        ms, cnt = op.profile_read(name)
+        if cnt:
+            kern[name] = {"total_ms": ms, "launches": cnt, "avg_us": 1e3 * ms / cnt}
+    return kern
+
+
+def solve_stats(infos, decode_info, count):
+    recs = [decode_info(i, count) for i in infos]
+    return (sum(r["iters"] for rec in recs for r in rec), sorted({r["status"] for rec in recs for r in rec}),
+            max(r["relres"] for rec in recs for r in rec))
+
+
+def timed_solves(op, B, nrhs, opts, steps, warmup, decode_info, count, backward=None):
+    """warmup + timed steps of solve (and optional backward); returns (seconds, infos)."""
+    import torch
+    for _ in range(warmup):
+        X, _ = op.solve(B, nrhs, **opts)
+        if backward is not None:
+            op.solve_backward(X, backward, nrhs, **opts)
+    torch.cuda.synchronize()
+    op.profile_enable(True)
+    infos = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        X, info = op.solve(B, nrhs, **opts)
+        infos.append(info)
+        if backward is not None:
+            out = op.solve_backward(X, backward, nrhs, **opts)
+            infos.append(out[-1])
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, infos
+
+
+def run_uneven_batch(args):
+    """256 uneven K1(x)K2 + s2 I systems: forward solve + adjoint backward per step."""
+    import torch
+    import workloads as wl
+    from paper_2309_03060_amd import KronOperator, SystemSpec, decode_info
+    dev = torch.device("cuda:0")
+    w = wl.config3()
+    specs = [SystemSpec(factors=[[torch.tensor(f, device=dev) for f in s.factors[0]]], sigma2=s.sigma2)
+             for s in w.systems]
+    op = KronOperator(specs, prec="fp32")
+    B = torch.cat([torch.tensor(b.reshape(-1), device=dev) for b in w.B]).contiguous()
+    G = torch.cat([torch.tensor(x.reshape(-1), device=dev) for x in w.W]).contiguous()
+    opts = dict(tol=1e-5, max_iters=20000, prec="fp32", inner_tol=0.1, check_every=32)
+    nsys = len(w.systems)
+    dt, infos = timed_solves(op, B, 1, opts, args.steps, args.warmup, decode_info, nsys, backward=G)
+    rhs_iters, statuses, worst = solve_stats(infos, decode_info, nsys)
+    kern = kernel_table(op, ["resident"])
+    op.profile_enable(False)
+    # algorithmic FP32 MFMA work of the resident kernel: per item iteration 2 n (n1 + n2)
+    # flops, summed over the items' iteration counts
+    iters_per_sys = np.zeros(nsys)
+    for info in infos:
+        for k, r in enumerate(decode_info(info, nsys)):
+            iters_per_sys[k] += r["iters"]
+    flops = sum(it * 2.0 * s.n * (s.dims[0] + s.dims[1]) for it, s in zip(iters_per_sys, w.systems))
+    roof = None
+    if "resident" in kern:
+        t = kern["resident"]["total_ms"] * 1e-3
+        ach = flops / t / 1e12
+        roof = {"kernel": "resident", "bound": "mfma", "achieved": round(ach, 3), "peak": FP32_MFMA_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(ach / FP32_MFMA_PEAK_TFLOPS, 4), "traffic": None,
+                "flops_per_launch": flops / kern["resident"]["launches"],
+                "avg_launch_us": round(kern["resident"]["avg_us"], 1), "launches": kern["resident"]["launches"]}
+    cpu = None
+    if not args.no_cpu:
+        from oracle import cg as ocg
+        from oracle import kron
+        sample = list(range(0, nsys, 16))
+        t0 = time.perf_counter()
+        tot = 0
+        for k in sample:
+            s = w.systems[k]
+            res = ocg.cg(lambda V: kron.mvm(s.factors, V, s.sigma2), w.B[k], 1e-5, 20000)
+            tot += int(res.iters.sum())
+        dtc = time.perf_counter() - t0
+        cpu = {"value": tot / dtc, "unit": "RHS*iters/s", "cores": _cores(), "kind": "oracle",
+               "sample": f"numpy float64 CG to 1e-5 on {len(sample)} of the {nsys} systems "
+                         f"({tot} RHS*iters in {dtc:.2f} s)"}
+    op.close()
+    return {"metric": METRIC, "value": round(rhs_iters / dt, 1), "unit": "RHS*iters/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * dt / args.steps, 3),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "256 independent K1(x)K2+s2 I systems, dims U{16..128}, RBF l~U[0.1,0.5], "
+                                   "s2~U[0.01,0.1], 1 RHS each; forward solve to 1e-5 + adjoint backward "
+                                   "(second solve + factor/sigma2 gradients) per step; FP32 resident kernel with "
+                                   "FP64 reliable updates", "systems": nsys,
+                       "unknowns": int(sum(s.n for s in w.systems)),
+                       "rhs_iters_per_step": rhs_iters // max(1, args.steps), "statuses": statuses,
+                       "worst_relres": worst, "parallelism": "single GPU"},
+            "roofline": roof, "cpu_baseline": cpu}
+
+
+def _cores():
+    try:
+        from threadpoolctl import threadpool_info
+        return int(max([p.get("num_threads", 1) for p in threadpool_info()] or [1]))
+    except Exception:
+        return os.cpu_count() or 1
+
+
+def run_single(args, name):
+    """Large single-system workloads: 256^3 x 8 RHS (mixed) or sum of 4 1024^2 terms + diag (BF16)."""
+    import torch
+    import workloads as wl
+    from paper_2309_03060_amd import KronOperator, SystemSpec, decode_info
+    dev = torch.device("cuda:0")
+    if name == "c4":
+        w = wl.config4()
+        prec, tol, label = args.prec or "fp32", 1e-6, "K1(x)K2(x)K3+0.05I RBF l=0.15, 256^3, 8 RHS, to 1e-6"
+    elif name == "c5":
+        w = wl.config5()
+        prec, tol, label = args.prec or "bf16", 1e-6, "sum_4 U_j(x)V_j + diag(d), Wishart 1024^2, 16 RHS, to 1e-6"
+    else:
+        w = wl.config1()
+        prec, tol, label = "fp64", 1e-10, "K1(x)K2+0.1I RBF l=0.2, 64^2, 1 RHS, FP64 to 1e-10"
+    s = w.systems[0]
+    nrhs = w.B[0].shape[0]
+    spec = SystemSpec(factors=[[torch.tensor(f, device=dev) for f in row] for row in s.factors], sigma2=s.sigma2,
+                      diag=None if s.diag is None else torch.tensor(s.diag, device=dev))
+    op = KronOperator([spec], prec="fp32" if prec == "fp64" else prec)
+    B = torch.tensor(w.B[0], device=dev).reshape(-1).contiguous()
+    if args.autotune:
+        op.autotune(nrhs)
+    opts = dict(tol=tol, max_iters=60000, prec=prec, inner_tol=0.1, check_every=32)
+    G = torch.tensor(w.W[0], device=dev).reshape(-1).contiguous() if (name == "c5" and w.W) else None
+    dt, infos = timed_solves(op, B, nrhs, opts, args.steps, args.warmup, decode_info, nrhs, backward=G)
+    rhs_iters, statuses, worst = solve_stats(infos, decode_info, nrhs)
+    names = ["slab23", "contract_rows", "contract_mid", "contract_last", "update"]
+    kern = kernel_table(op, names)
+    op.profile_enable(False)
+    n = s.n
+    # algorithmic FLOPs of one RHS*iteration of the working-precision MVM (Table 2 cost, per mode)
+    flop_rhs_it = 2.0 * n * sum(sum(f.shape[0] for f in row) for row in s.factors)
+    per_kernel = {k: {"avg_us": round(v["avg_us"], 2), "launches": v["launches"]} for k, v in kern.items()}
+    contract_ms = sum(v["total_ms"] for k, v in kern.items() if k != "update")
+    roof = None
+    if contract_ms > 0:
+        ach = flop_rhs_it * rhs_iters / (contract_ms * 1e-3) / 1e12
+        peak = {"fp32": FP32_MFMA_PEAK_TFLOPS, "bf16": 2500.0, "bf16x3": 2500.0, "fp64": 78.6}[prec]
+        roof = {"kernel": "contraction passes (all modes)", "bound": "mfma", "achieved": round(ach, 2), "peak": peak,
+                "unit": "TFLOP/s", "frac": round(ach / peak, 4), "traffic": None, "per_kernel": per_kernel,
+                "note": "bf16x3 issues 6 bf16 products per useful one; its frac is against the bf16 peak"}
+    tts = None
+    if not args.no_tts and prec != "fp64":
+        res = {}
+        for lab, o in (("mixed", dict(opts)), ("fp64_cg", dict(tol=tol, max_iters=60000, prec="fp64", check_every=32))):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            X, info = op.solve(B, nrhs, **o)
+            torch.cuda.synchronize()
+            rec = decode_info(info, nrhs)
+            res[lab] = {"seconds": round(time.perf_counter() - t1, 3), "iters_max": max(r["iters"] for r in rec),
+                        "relres_max": max(r["relres"] for r in rec), "status": sorted({r["status"] for r in rec})}
+        res["speedup"] = round(res["fp64_cg"]["seconds"] / res["mixed"]["seconds"], 3)
+        tts = res
+    cpu = None
+    if not args.no_cpu:
+        from oracle import cg as ocg
+        from oracle import kron
+        iters = 3 if name in ("c4", "c5") else 50
+        t0 = time.perf_counter()
+        res = ocg.cg(lambda V: kron.mvm(s.factors, V, s.sigma2, s.diag), w.B[0][:1], tol=1e-30, max_iters=iters)
+        dtc = time.perf_counter() - t0
+        cpu = {"value": int(res.iters.sum()) / dtc, "unit": "RHS*iters/s", "cores": _cores(), "kind": "oracle",
+               "sample": f"numpy float64 CG, 1 RHS x {iters} iterations in {dtc:.2f} s"}
+    op.close()
+    return {"metric": METRIC, "value": round(rhs_iters / dt, 1), "unit": "RHS*iters/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * dt / args.steps, 3),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": prec, "data": "synthetic",
+            "config": {"workload": label + (" (+ adjoint backward per step)" if G is not None else ""), "n": n,
+                       "nrhs": nrhs, "rhs_iters_per_step": rhs_iters // max(1, args.steps), "statuses": statuses,
+                       "worst_relres": worst, "parallelism": "single GPU"},
+            "roofline": roof, "cpu_baseline": cpu, "mixed_vs_fp64": tts}
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    if args.workload == "c3":
+        print(json.dumps(run_uneven_batch(args)))
+        return
+    if args.workload in ("c1", "c4", "c5"):
+        print(json.dumps(run_single(args, args.workload)))
+        return
     import torch
     import workloads as wl
     from paper_2309_03060_amd import KronOperator, SystemSpec, decode_info
