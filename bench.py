@@ -58,11 +58,16 @@ def parse():
     ap.add_argument("--cpu-iters", type=int, default=40, help="oracle CG iterations timed on the host")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tts", action="store_true", help="skip the mixed-vs-FP64 time-to-solution runs")
-    ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
+                    help="skip the tile autotuner (cola_autotune) at operator setup")
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"],
                     help="c2 (default): 64^3 x 32 RHS; c3: 256 uneven systems with backward; c4: 256^3 x 8 RHS; "
                          "c5: sum of 4 1024^2 terms + diag with backward; c1: 64^2 FP64")
     ap.add_argument("--prec", default=None, help="working precision for c4/c5 (fp32, bf16x3, bf16)")
+    ap.add_argument("--counters", action="store_true",
+                    help="short run for hardware-counter collection: a 256 MiB device copy (reference for "
+                         "the HBM byte counters), then one solve capped at --max-iters iterations")
+    ap.add_argument("--max-iters", type=int, default=20000)
     return ap.parse_args()
 
 
@@ -270,11 +275,35 @@ def run_single(args, name):
             "roofline": roof, "cpu_baseline": cpu, "mixed_vs_fp64": tts}
 
 
+def run_counters(args):
+    """Short run for rocprofv3 --pmc: reference copy of known size, then a capped solve."""
+    import torch
+    import workloads as wl
+    from paper_2309_03060_amd import KronOperator, SystemSpec
+    dev = torch.device("cuda:0")
+    a = torch.ones(64 << 20, dtype=torch.float32, device=dev)    # 256 MiB
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    w = wl.config2(m=args.m, nrhs=args.nrhs)
+    s = w.systems[0]
+    spec = SystemSpec(factors=[[torch.tensor(f, device=dev) for f in s.factors[0]]], sigma2=s.sigma2)
+    op = KronOperator([spec], prec="fp32")
+    B = torch.tensor(w.B[0], device=dev).reshape(-1).contiguous()
+    op.solve(B, args.nrhs, tol=args.tol, max_iters=args.max_iters, prec="fp32", inner_tol=0.1, check_every=0)
+    torch.cuda.synchronize()
+    op.close()
+    print(json.dumps({"counters_run": "done", "copy_bytes": 2 * (64 << 20) * 4, "max_iters": args.max_iters}))
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    if args.counters:
+        run_counters(args)
+        return
     if args.workload == "c3":
         print(json.dumps(run_uneven_batch(args)))
         return

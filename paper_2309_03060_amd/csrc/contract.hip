@@ -106,13 +106,20 @@ __global__ __launch_bounds__(kThreads) void k_contract(PassArgs a) {
     constexpr int MT = 32 * WM, NT = 32 * WN, KT = P::KT, KP = P::KP, NS = P::NS;
     constexpr int EPAD = sizeof(V) == 8 ? 2 : 4;
     constexpr int EW = 16 * WN + EPAD;                       // epilogue row stride (elements)
-    constexpr size_t AB_BYTES = sizeof(L) * NS * (size_t)(MT + NT) * KP;
+    // COLS, FP32/FP64: the vector tile is staged as [k][n] (as it lies in
+    // memory) with a row pitch of 16 (mod 64) banks, which keeps both the
+    // 16-byte staging writes and the MFMA operand reads free of bank
+    // conflicts; the bf16 policies keep [n][k] for their 8-wide k operands.
+    constexpr bool BKN = !ROWS && !IsBf<P>::value;
+    constexpr int NTP = NT + (sizeof(L) == 8 ? 8 : 16);
+    constexpr size_t B_ELEMS = BKN ? (size_t)KT * NTP : (size_t)NT * KP;
+    constexpr size_t AB_BYTES = sizeof(L) * NS * ((size_t)MT * KP + B_ELEMS);
     constexpr size_t E_BYTES = sizeof(V) * 4 * 16 * (size_t)EW;
     constexpr size_t SMEM = AB_BYTES > E_BYTES ? AB_BYTES : E_BYTES;
     __shared__ __attribute__((aligned(16))) char smem[SMEM];
     __shared__ double red[4];
     L* As = (L*)smem;                      // [NS][MT][KP]
-    L* Bs = As + NS * MT * KP;             // [NS][NT][KP]
+    L* Bs = As + NS * MT * KP;             // [NS][NT][KP], or [KT][NTP] when BKN
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
@@ -152,6 +159,8 @@ __global__ __launch_bounds__(kThreads) void k_contract(PassArgs a) {
 
     double beta_blk = 0.0;
     if (!ROWS && a.pnew) beta_blk = a.cg[g / a.a_per_rhs].beta;
+    // every element of this block's output tile exists and rows are 16-byte aligned
+    const bool tile_full = !ROWS && bvec && (m0 + MT <= nk) && (n0 + NT <= a.B);
 
     // stage a k-contiguous [rows][KT] tile of a factor (4 elements per step)
     auto stage_factor = [&](L* dst, const Fac* Kp, int64_t r0, int rows, int k0) {
@@ -176,6 +185,31 @@ __global__ __launch_bounds__(kThreads) void k_contract(PassArgs a) {
             }
         }
     };
+
+    // The CG epilogue's streaming operands (r and p_old) do not depend on the
+    // contraction: issue their loads now so they arrive while the MFMA loop runs.
+    constexpr bool PREF = false;   // measured slower: the extra registers cost more occupancy than the early loads gained
+    constexpr int CHN = (16 * WN) / 4;                       // 4-column chunks per staged row
+    V pre_r[PREF ? WM : 1][PREF ? WN : 1][4], pre_p[PREF ? WM : 1][PREF ? WN : 1][4];
+    const bool use_pref = PREF && a.epi == EPI_CG && bvec;
+    if constexpr (PREF) {
+        if (use_pref) {
+#pragma unroll
+            for (int i = 0; i < WM; ++i)
+#pragma unroll
+                for (int c = 0; c < WN; ++c) {
+                    const int t2 = lane + 64 * c;
+                    const int r = t2 / CHN, c4 = (t2 % CHN) * 4;
+                    const int64_t m = m0 + wm * WM * 16 + i * 16 + r;
+                    const int64_t n = n0 + wn * WN * 16 + c4;
+                    if (m < nk && n + 3 < a.B) {
+                        const int64_t idx = g * (int64_t)nk * a.B + m * a.B + n;
+                        load4((const V*)a.Er + idx, pre_r[i][c]);
+                        load4((const V*)a.Ep + idx, pre_p[i][c]);
+                    }
+                }
+        }
+    }
 
     for (int t = 0; t < a.nsum; ++t) {
         const int tt = (a.nsum > 1) ? t : tout;
@@ -222,6 +256,31 @@ __global__ __launch_bounds__(kThreads) void k_contract(PassArgs a) {
             } else {
                 // A: factor rows K[i, k], B: vector X[g, k, b] (b contiguous) stored as [b][k]
                 stage_factor(As, Kp, m0, MT, k0);
+                if (BKN && tile_full && k0 + KT <= nk) {
+                    // whole tile in range: straight-line 16-byte loads, all issued before use
+                    constexpr int NE = (KT * (NT / 4) + kThreads - 1) / kThreads;
+                    V v[NE][4], rr4[NE][4];
+#pragma unroll
+                    for (int q = 0; q < NE; ++q) {
+                        const int e = tid + kThreads * q;
+                        if (e < KT * (NT / 4)) {
+                            const int k = e / (NT / 4), n = (e % (NT / 4)) * 4;
+                            const int64_t idx = (g * nk + k0 + k) * a.B + n0 + n;
+                            load4(Xp + idx, v[q]);
+                            if (a.pnew) load4(Rp + idx, rr4[q]);
+                        }
+                    }
+#pragma unroll
+                    for (int q = 0; q < NE; ++q) {
+                        const int e = tid + kThreads * q;
+                        if (e < KT * (NT / 4)) {
+                            const int k = e / (NT / 4), n = (e % (NT / 4)) * 4;
+#pragma unroll
+                            for (int c = 0; c < 4; ++c)
+                                Bs[k * NTP + n + c] = (L)(a.pnew ? pnew_of(rr4[q][c], v[q][c], beta_blk) : v[q][c]);
+                        }
+                    }
+                } else
                 for (int e = tid; e < KT * (NT / 4); e += kThreads) {
                     const int k = e / (NT / 4), n = (e % (NT / 4)) * 4;
                     const int gk = k0 + k;
@@ -246,12 +305,17 @@ __global__ __launch_bounds__(kThreads) void k_contract(PassArgs a) {
                                 }
                         }
                     }
+                    if constexpr (BKN) {
 #pragma unroll
-                    for (int c = 0; c < 4; ++c) {
-                        L parts[NS];
-                        split_value<P>(v[c], parts);
+                        for (int c = 0; c < 4; ++c) Bs[k * NTP + n + c] = (L)v[c];
+                    } else {
 #pragma unroll
-                        for (int sp = 0; sp < NS; ++sp) Bs[(sp * NT + n + c) * KP + k] = parts[sp];
+                        for (int c = 0; c < 4; ++c) {
+                            L parts[NS];
+                            split_value<P>(v[c], parts);
+#pragma unroll
+                            for (int sp = 0; sp < NS; ++sp) Bs[(sp * NT + n + c) * KP + k] = parts[sp];
+                        }
                     }
                 }
             }
@@ -265,8 +329,10 @@ __global__ __launch_bounds__(kThreads) void k_contract(PassArgs a) {
                     for (int i = 0; i < WM; ++i)
                         av[i] = As[(wm * WM * 16 + i * 16 + (lane & 15)) * KP + kk + (lane >> 4)];
 #pragma unroll
-                    for (int j = 0; j < WN; ++j)
-                        bv[j] = Bs[(wn * WN * 16 + j * 16 + (lane & 15)) * KP + kk + (lane >> 4)];
+                    for (int j = 0; j < WN; ++j) {
+                        if constexpr (BKN) bv[j] = Bs[(kk + (lane >> 4)) * NTP + wn * WN * 16 + j * 16 + (lane & 15)];
+                        else bv[j] = Bs[(wn * WN * 16 + j * 16 + (lane & 15)) * KP + kk + (lane >> 4)];
+                    }
 #pragma unroll
                     for (int i = 0; i < WM; ++i)
 #pragma unroll
@@ -323,7 +389,68 @@ __global__ __launch_bounds__(kThreads) void k_contract(PassArgs a) {
             for (int v = 0; v < 4; ++v)
                 Ew[acc_row(acc[i][j][v], lane, v) * EW + j * 16 + (lane & 15)] = (V)acc[i][j][v];
         __syncthreads();
-        for (int t2 = lane; t2 < 16 * CH; t2 += 64) {
+        if (tile_full) {
+            // uniform fast path: every chunk is a full 16-byte vector; all loads first
+            V u4[WN][4], w4v[WN][4], d4v[WN][4];
+            const bool need_p = a.epi != EPI_STORE, need_r = a.epi == EPI_CG || a.epi == EPI_RESID ||
+                                                             a.epi == EPI_RESID_CG;
+#pragma unroll
+            for (int cc = 0; cc < WN; ++cc) {
+                const int t2 = lane + 64 * cc;
+                const int r = t2 / CH, c4 = (t2 % CH) * 4;
+                const int64_t m = m0 + wm * WM * 16 + i * 16 + r;
+                const int64_t e0 = m * a.B + n0 + wn * WN * 16 + c4;
+                const int64_t idx = g * (int64_t)nk * a.B + e0;
+                if (need_p) load4((const V*)a.Ep + idx, u4[cc]);
+                if (need_r) load4((const V*)a.Er + idx, w4v[cc]);
+                if (need_p && a.dvec) load4((const V*)a.dvec + e0, d4v[cc]);
+            }
+#pragma unroll
+            for (int cc = 0; cc < WN; ++cc) {
+                const int t2 = lane + 64 * cc;
+                const int r = t2 / CH, c4 = (t2 % CH) * 4;
+                const int64_t m = m0 + wm * WM * 16 + i * 16 + r;
+                const int64_t e0 = m * a.B + n0 + wn * WN * 16 + c4;
+                const int64_t idx = g * (int64_t)nk * a.B + e0;
+                V val[4], out[4];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) val[c] = Ew[r * EW + c4 + c];
+                if (a.epi == EPI_STORE) {
+                    store4(Y + idx, val);
+                    continue;
+                }
+                V dg[4];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) dg[c] = (V)a.sigma2 + (a.dvec ? d4v[cc][c] : (V)0);
+                if (a.epi == EPI_CG) {
+                    V pn[4];
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        pn[c] = pnew_of(w4v[cc][c], u4[cc][c], beta_e);
+                        out[c] = val[c] + dg[c] * pn[c];
+                        dot += (double)pn[c] * (double)out[c];
+                    }
+                    store4(Y + idx, out);
+                    store4((V*)a.Epout + idx, pn);
+                } else if (a.epi == EPI_MATVEC) {
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) out[c] = val[c] + dg[c] * u4[cc][c];
+                    store4(Y + idx, out);
+                } else {
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        out[c] = w4v[cc][c] - (val[c] + dg[c] * u4[cc][c]);
+                        dot += (double)out[c] * (double)out[c];
+                    }
+                    store4(Y + idx, out);
+                }
+            }
+            __syncthreads();
+            continue;
+        }
+#pragma unroll
+        for (int cc = 0; cc < WN; ++cc) {               // 16 * CH = 64 * WN chunks: WN per lane
+            const int t2 = lane + 64 * cc;
             const int r = t2 / CH, c4 = (t2 % CH) * 4;
             const int64_t m = m0 + wm * WM * 16 + i * 16 + r;
             const int64_t n = n0 + wn * WN * 16 + c4;
@@ -351,8 +478,18 @@ __global__ __launch_bounds__(kThreads) void k_contract(PassArgs a) {
                     for (int c = 0; c < 4; ++c) dg[c] = (V)a.sigma2;
                     if (full) {
                         if (a.dvec) { V d4[4]; load4((const V*)a.dvec + e0, d4); for (int c = 0; c < 4; ++c) dg[c] += d4[c]; }
-                        load4((const V*)a.Ep + idx, u);
-                        if (a.epi != EPI_MATVEC) load4((const V*)a.Er + idx, w4);
+                        if constexpr (PREF) {
+                            if (use_pref) {
+#pragma unroll
+                                for (int c = 0; c < 4; ++c) { u[c] = pre_p[i][cc][c]; w4[c] = pre_r[i][cc][c]; }
+                            } else {
+                                load4((const V*)a.Ep + idx, u);
+                                if (a.epi != EPI_MATVEC) load4((const V*)a.Er + idx, w4);
+                            }
+                        } else {
+                            load4((const V*)a.Ep + idx, u);
+                            if (a.epi != EPI_MATVEC) load4((const V*)a.Er + idx, w4);
+                        }
                     } else {
                         for (int c = 0; c < cnt; ++c) {
                             if (a.dvec) dg[c] += ((const V*)a.dvec)[e0 + c];

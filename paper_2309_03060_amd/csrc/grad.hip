@@ -11,6 +11,8 @@
 // sums the slices in fixed order.  The diagonal and sigma2 gradients are
 // -sum_r lambda_r * x_r and its total.
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -309,11 +311,16 @@ int32_t autotune_op(cola_op_s* op, int nrhs, hipStream_t st) {
                     }
                 }
                 op->tiles[key] = bestc;
+                if (std::getenv("COLA_VERBOSE"))
+                    std::fprintf(stderr, "cola_autotune: prec %d %s nk %lld B %lld lead %lld -> tile %dx%d (%.1f us)\n",
+                                 prec, rows ? "rows" : "cols", (long long)nk, (long long)(rows ? 1 : trail),
+                                 (long long)lead, 32 * bestc.wm, 32 * bestc.wn, 1e3 * best / 5);
             }
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    op->tiles_version += 1;
     return COLA_OK;
 }
 

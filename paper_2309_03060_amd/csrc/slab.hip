@@ -4,15 +4,19 @@
 // mode-3 products act on each n2 x n3 slab X[i1] independently:
 // T[i1] = K2 X[i1] K3^T (the per-mode evaluation behind the Kronecker MVM
 // cost of Table 2).  When a slab fits in LDS (n2, n3 <= 64) both products
-// are done there: the slab is read once, the intermediate K2-free product
-// never leaves the CU, and T is written once.  Blocks are persistent over a
-// range of slabs so the two factors are staged in LDS once per block.
+// are done there: the slab is read once, the intermediate product never
+// leaves the CU, and T is written once.  Blocks are persistent over a range
+// of slabs so the two factors are staged in LDS once per block, and the next
+// slab's loads are issued while the current one is being multiplied.
 #include "slab.h"
 
 namespace cola {
 
-struct SlabF32 { using V = float;  using Acc = floatx4;  static constexpr int KP = 64 + 4; };
-struct SlabF64 { using V = double; using Acc = doublex4; static constexpr int KP = 64 + 2; };
+// UP = 64 + 4 keeps the block at 52 KB of LDS (3 blocks per CU); a bank-free
+// pitch of 80 for the second product's operand reads measured slower because
+// it drops occupancy to 2 blocks.
+struct SlabF32 { using V = float;  using Acc = floatx4;  static constexpr int KP = 64 + 4, UP = 64 + 4; };
+struct SlabF64 { using V = double; using Acc = doublex4; static constexpr int KP = 64 + 2, UP = 64 + 2; };
 
 __device__ inline floatx4 smma(float a, float b, floatx4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
@@ -37,17 +41,20 @@ __device__ inline void sstore4(double* p, const double* v) {
     *(d2*)(p + 2) = d2{v[2], v[3]};
 }
 
-template <class S>
+// FULL: 64 x 64 slabs (16-byte loads); PNEW: the slab is the CG direction
+// r + beta p.  Both are template parameters so the prefetch below is
+// straight-line code the compiler can leave in flight across the products.
+template <class S, bool FULL, bool PNEW>
 __global__ __launch_bounds__(kThreads) void k_slab23(SlabArgs a) {
     using V = typename S::V;
     using Acc = typename S::Acc;
-    constexpr int D = 64, KP = S::KP;
+    constexpr int D = 64, KP = S::KP, UP = S::UP;
     __shared__ __attribute__((aligned(16))) V K2s[D * KP];
     __shared__ __attribute__((aligned(16))) V K3s[D * KP];
-    __shared__ __attribute__((aligned(16))) V Ps[D * KP];   // slab, later the output T
-    __shared__ __attribute__((aligned(16))) V Ut[D * KP];   // (X K3^T) stored transposed
+    __shared__ __attribute__((aligned(16))) V Ut[D * UP];   // U = P K3^T (row-major), then the output T
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
+    const int lr = lane & 15, lq = lane >> 4;
     const int n2 = a.n2, n3 = a.n3;
     const int64_t slab = (int64_t)n2 * n3;
     const int term = blockIdx.y;
@@ -56,7 +63,7 @@ __global__ __launch_bounds__(kThreads) void k_slab23(SlabArgs a) {
     V* Yt = (V*)a.Y + (int64_t)term * a.y_tstride;
     const V* X = (const V*)a.X;
     const V* R = (const V*)a.R;
-    const bool full = (n2 == D && n3 == D);
+    constexpr bool full = FULL;
 
     for (int e = tid; e < D * D; e += kThreads) {
         const int r = e / D, c = e % D;
@@ -64,39 +71,76 @@ __global__ __launch_bounds__(kThreads) void k_slab23(SlabArgs a) {
         K3s[r * KP + c] = (r < n3 && c < n3) ? K3[r * n3 + c] : (V)0;
     }
 
-    for (int64_t sl = blockIdx.x; sl < a.nslabs; sl += gridDim.x) {
-        const int64_t rhs = sl / a.a_per_rhs;
-        if (a.gate && !a.gate[rhs * a.gate_stride]) continue;
-        const double be = a.pnew ? a.cg[rhs].beta : 0.0;
+    auto next_active = [&](int64_t sl) -> int64_t {
+        while (sl < a.nslabs && a.gate && !a.gate[(sl / a.a_per_rhs) * a.gate_stride]) sl += gridDim.x;
+        return sl;
+    };
+    // The first product U = P K3^T is done per wave on a 16-row strip of the
+    // slab, reading its A operand straight from global memory.  The inner
+    // (column) index is permuted so each lane loads 4 consecutive columns at
+    // once: at MFMA step s = 4u + c the lane group lq supplies column
+    // 16u + 4 lq + c, and the B operand from K3 uses the same permutation.
+    const int arow = 16 * wave + lr;             // slab row of this lane's A values
+    V pv[16], rv[16];
+    auto load_strip = [&](int64_t sl) {
         const int64_t base = sl * slab;
-        __syncthreads();                     // previous slab's LDS reads are done
-        if (full) {
-            for (int e = tid; e < D * D / 4; e += kThreads) {
-                const int r = e / (D / 4), c = (e % (D / 4)) * 4;
-                V v[4];
-                sload4(X + base + r * D + c, v);
-                if (a.pnew) {
-                    V rr[4];
-                    sload4(R + base + r * D + c, rr);
+        if constexpr (FULL) {
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) v[q] = pnew_of(rr[q], v[q], be);
-                }
-#pragma unroll
-                for (int q = 0; q < 4; ++q) Ps[r * KP + c + q] = v[q];
+            for (int u = 0; u < 4; ++u) {
+                const int64_t off = base + arow * D + 16 * u + 4 * lq;
+                sload4(X + off, pv + 4 * u);
+                if constexpr (PNEW) sload4(R + off, rv + 4 * u);
             }
         } else {
-            for (int e = tid; e < D * D; e += kThreads) {
-                const int r = e / D, c = e % D;
-                V v = 0;
-                if (r < n2 && c < n3) {
-                    v = X[base + r * n3 + c];
-                    if (a.pnew) v = pnew_of(R[base + r * n3 + c], v, be);
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const int col = 16 * u + 4 * lq + c;
+                    const bool ok = arow < n2 && col < n3;
+                    const int64_t off = base + (ok ? arow * n3 + col : 0);
+                    pv[4 * u + c] = X[off];
+                    if constexpr (PNEW) rv[4 * u + c] = R[off];
+                    if (!ok) { pv[4 * u + c] = (V)0; if constexpr (PNEW) rv[4 * u + c] = (V)0; }
                 }
-                Ps[r * KP + c] = v;
-            }
         }
-        __syncthreads();
-        // U = P K3^T  (U[a][c] = sum_k P[a][k] K3[c][k]); wave tile 32 x 32
+    };
+
+    int64_t sl = next_active(blockIdx.x);
+    __syncthreads();
+    if (sl < a.nslabs) load_strip(sl);
+    while (sl < a.nslabs) {
+        const int64_t nx = next_active(sl + gridDim.x);
+        V av[16];
+        if constexpr (PNEW) {
+            const double be = a.cg[sl / a.a_per_rhs].beta;
+#pragma unroll
+            for (int q = 0; q < 16; ++q) av[q] = pnew_of(rv[q], pv[q], be);
+        } else {
+#pragma unroll
+            for (int q = 0; q < 16; ++q) av[q] = pv[q];
+        }
+        // U strip: rows 16 wave .. +15, all 64 columns (4 MFMA tiles)
+        Acc acc1[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc1[j] = Acc{0, 0, 0, 0};
+#pragma unroll
+        for (int st = 0; st < 16; ++st) {
+            const int kcol = 16 * (st >> 2) + 4 * lq + (st & 3);
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                acc1[j] = smma(av[st], K3s[(16 * j + lr) * KP + kcol], acc1[j]);
+        }
+        load_strip(nx < a.nslabs ? nx : sl);       // next strip in flight during the second product
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = 16 * wave + acc_row(acc1[j][v], lane, v);
+                Ut[row * UP + 16 * j + lr] = (V)acc1[j][v];
+            }
+        __syncthreads();                           // U complete
+        // T = K2 U  (T[b][c] = sum_a K2[b][a] U[a][c]); wave tile 32 x 32
         Acc acc[2][2];
 #pragma unroll
         for (int i = 0; i < 2; ++i)
@@ -104,16 +148,17 @@ __global__ __launch_bounds__(kThreads) void k_slab23(SlabArgs a) {
             for (int j = 0; j < 2; ++j) acc[i][j] = Acc{0, 0, 0, 0};
 #pragma unroll 4
         for (int k = 0; k < D; k += 4) {
-            V av[2], bv[2];
+            V a2[2], b2[2];
 #pragma unroll
-            for (int i = 0; i < 2; ++i) av[i] = Ps[(32 * wm + 16 * i + (lane & 15)) * KP + k + (lane >> 4)];
+            for (int i = 0; i < 2; ++i) a2[i] = K2s[(32 * wm + 16 * i + lr) * KP + k + lq];
 #pragma unroll
-            for (int j = 0; j < 2; ++j) bv[j] = K3s[(32 * wn + 16 * j + (lane & 15)) * KP + k + (lane >> 4)];
+            for (int j = 0; j < 2; ++j) b2[j] = Ut[(k + lq) * UP + 32 * wn + 16 * j + lr];
 #pragma unroll
             for (int i = 0; i < 2; ++i)
 #pragma unroll
-                for (int j = 0; j < 2; ++j) acc[i][j] = smma(av[i], bv[j], acc[i][j]);
+                for (int j = 0; j < 2; ++j) acc[i][j] = smma(a2[i], b2[j], acc[i][j]);
         }
+        __syncthreads();                           // U reads done
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -121,53 +166,24 @@ __global__ __launch_bounds__(kThreads) void k_slab23(SlabArgs a) {
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int row = 32 * wm + 16 * i + acc_row(acc[i][j][v], lane, v);
-                    const int col = 32 * wn + 16 * j + (lane & 15);
-                    Ut[col * KP + row] = (V)acc[i][j][v];
+                    const int col = 32 * wn + 16 * j + lr;
+                    Ut[row * UP + col] = (V)acc[i][j][v];
                 }
         __syncthreads();
-        // T = K2 U  (T[b][c] = sum_a K2[b][a] U[a][c])
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-            for (int j = 0; j < 2; ++j) acc[i][j] = Acc{0, 0, 0, 0};
-#pragma unroll 4
-        for (int k = 0; k < D; k += 4) {
-            V av[2], bv[2];
-#pragma unroll
-            for (int i = 0; i < 2; ++i) av[i] = K2s[(32 * wm + 16 * i + (lane & 15)) * KP + k + (lane >> 4)];
-#pragma unroll
-            for (int j = 0; j < 2; ++j) bv[j] = Ut[(32 * wn + 16 * j + (lane & 15)) * KP + k + (lane >> 4)];
-#pragma unroll
-            for (int i = 0; i < 2; ++i)
-#pragma unroll
-                for (int j = 0; j < 2; ++j) acc[i][j] = smma(av[i], bv[j], acc[i][j]);
-        }
-        // stage T row-major in Ps (P is no longer read), then write it out
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-            for (int j = 0; j < 2; ++j)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int row = 32 * wm + 16 * i + acc_row(acc[i][j][v], lane, v);
-                    const int col = 32 * wn + 16 * j + (lane & 15);
-                    Ps[row * KP + col] = (V)acc[i][j][v];
-                }
-        __syncthreads();
+        const int64_t base = sl * slab;
         if (full) {
             for (int e = tid; e < D * D / 4; e += kThreads) {
                 const int r = e / (D / 4), c = (e % (D / 4)) * 4;
                 V v[4];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) v[q] = Ps[r * KP + c + q];
+                for (int q = 0; q < 4; ++q) v[q] = Ut[r * UP + c + q];
                 sstore4(Yt + base + r * D + c, v);
             }
         } else {
-            for (int e = tid; e < n2 * n3; e += kThreads) {
-                const int r = e / n3, c = e % n3;
-                Yt[base + e] = Ps[r * KP + c];
-            }
+            for (int e = tid; e < slab; e += kThreads) Yt[base + e] = Ut[(e / n3) * UP + (e % n3)];
         }
+        __syncthreads();                           // T read out of U before the next slab writes U
+        sl = nx;
     }
 }
 
@@ -176,15 +192,22 @@ bool slab_supported(int prec, int64_t n2, int64_t n3) {
 }
 
 hipError_t launch_slab23(int prec, const SlabArgs& a, hipStream_t s) {
-    const int64_t cap = (prec == COLA_PREC_FP64) ? 256 : 512;
+    const int64_t cap = (prec == COLA_PREC_FP64) ? 256 : 768;   // 1 (FP64) or 3 (FP32) blocks per CU
     const unsigned gx = (unsigned)(a.nslabs < cap ? a.nslabs : cap);
     dim3 grid(gx, (unsigned)a.nterms);
-    if (prec == COLA_PREC_FP32)
-        hipLaunchKernelGGL(k_slab23<SlabF32>, grid, dim3(kThreads), 0, s, a);
-    else if (prec == COLA_PREC_FP64)
-        hipLaunchKernelGGL(k_slab23<SlabF64>, grid, dim3(kThreads), 0, s, a);
-    else
-        return hipErrorInvalidValue;
+    const bool full = a.n2 == 64 && a.n3 == 64;
+    const bool pn = a.pnew != 0;
+#define COLA_SLAB_LAUNCH(S)                                                                              \
+    do {                                                                                                 \
+        if (full && pn) hipLaunchKernelGGL((k_slab23<S, true, true>), grid, dim3(kThreads), 0, s, a);    \
+        else if (full) hipLaunchKernelGGL((k_slab23<S, true, false>), grid, dim3(kThreads), 0, s, a);    \
+        else if (pn) hipLaunchKernelGGL((k_slab23<S, false, true>), grid, dim3(kThreads), 0, s, a);      \
+        else hipLaunchKernelGGL((k_slab23<S, false, false>), grid, dim3(kThreads), 0, s, a);             \
+    } while (0)
+    if (prec == COLA_PREC_FP32) COLA_SLAB_LAUNCH(SlabF32);
+    else if (prec == COLA_PREC_FP64) COLA_SLAB_LAUNCH(SlabF64);
+    else return hipErrorInvalidValue;
+#undef COLA_SLAB_LAUNCH
     return hipGetLastError();
 }
 
