@@ -65,10 +65,22 @@ def parse():
                          "c5: sum of 4 1024^2 terms + diag with backward; c1: 64^2 FP64")
     ap.add_argument("--prec", default=None, help="working precision for c4/c5 (fp32, bf16x3, bf16)")
     ap.add_argument("--counters", action="store_true",
-                    help="short run for hardware-counter collection: a 256 MiB device copy (reference for "
-                         "the HBM byte counters), then one solve capped at --max-iters iterations")
-    ap.add_argument("--max-iters", type=int, default=20000)
+                    help="short run for hardware-counter collection (c2, c4 or c5): set-up and autotuner, a "
+                         "256 MiB device copy (reference for the HBM byte counters), then one solve capped "
+                         "at --max-iters iterations")
+    ap.add_argument("--pmc-summary", nargs="+", default=None, metavar="CSV",
+                    help="summarise rocprofv3 --pmc CSV files of a --counters run of --workload (no GPU use)")
+    ap.add_argument("--trace-summary", nargs=3, default=None, metavar=("PREFIX", "CMD", "TITLE"),
+                    help="summarise rocprofv3 kernel-trace CSVs PREFIX_kernel_stats.csv / _kernel_trace.csv")
+    ap.add_argument("--pmc-out", default=None, help="with --pmc-summary: JSON file to merge the traffic record into")
+    ap.add_argument("--max-iters", type=int, default=None,
+                    help="cap on CG iterations per solve (default: the workload's own limit)")
     return ap.parse_args()
+
+
+def progress(msg):
+    """One line per finished piece of work, on stderr (the JSON result stays alone on stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def cpu_baseline(w, iters):
@@ -111,21 +123,23 @@ def solve_stats(infos, decode_info, count):
 def timed_solves(op, B, nrhs, opts, steps, warmup, decode_info, count, backward=None):
     """warmup + timed steps of solve (and optional backward); returns (seconds, infos)."""
     import torch
-    for _ in range(warmup):
+    for k in range(warmup):
         X, _ = op.solve(B, nrhs, **opts)
         if backward is not None:
             op.solve_backward(X, backward, nrhs, **opts)
-    torch.cuda.synchronize()
+        torch.cuda.synchronize()
+        progress(f"warmup step {k + 1}/{warmup} done")
     op.profile_enable(True)
     infos = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(steps):
+    for k in range(steps):
         X, info = op.solve(B, nrhs, **opts)
         infos.append(info)
         if backward is not None:
             out = op.solve_backward(X, backward, nrhs, **opts)
             infos.append(out[-1])
+        progress(f"timed step {k + 1}/{steps} enqueued")
     torch.cuda.synchronize()
     return time.perf_counter() - t0, infos
 
@@ -223,7 +237,7 @@ def run_single(args, name):
     B = torch.tensor(w.B[0], device=dev).reshape(-1).contiguous()
     if args.autotune:
         op.autotune(nrhs)
-    opts = dict(tol=tol, max_iters=60000, prec=prec, inner_tol=0.1, check_every=32)
+    opts = dict(tol=tol, max_iters=args.max_iters or 60000, prec=prec, inner_tol=0.1, check_every=32)
     G = torch.tensor(w.W[0], device=dev).reshape(-1).contiguous() if (name == "c5" and w.W) else None
     dt, infos = timed_solves(op, B, nrhs, opts, args.steps, args.warmup, decode_info, nrhs, backward=G)
     rhs_iters, statuses, worst = solve_stats(infos, decode_info, nrhs)
@@ -245,7 +259,8 @@ def run_single(args, name):
     tts = None
     if not args.no_tts and prec != "fp64":
         res = {}
-        for lab, o in (("mixed", dict(opts)), ("fp64_cg", dict(tol=tol, max_iters=60000, prec="fp64", check_every=32))):
+        for lab, o in (("mixed", dict(opts)), ("fp64_cg", dict(tol=tol, max_iters=args.max_iters or 60000, prec="fp64",
+                                                                   check_every=32))):
             torch.cuda.synchronize()
             t1 = time.perf_counter()
             X, info = op.solve(B, nrhs, **o)
@@ -253,6 +268,7 @@ def run_single(args, name):
             rec = decode_info(info, nrhs)
             res[lab] = {"seconds": round(time.perf_counter() - t1, 3), "iters_max": max(r["iters"] for r in rec),
                         "relres_max": max(r["relres"] for r in rec), "status": sorted({r["status"] for r in rec})}
+            progress(f"time-to-solution {lab}: {res[lab]['seconds']} s")
         res["speedup"] = round(res["fp64_cg"]["seconds"] / res["mixed"]["seconds"], 3)
         tts = res
     cpu = None
@@ -275,25 +291,186 @@ def run_single(args, name):
             "roofline": roof, "cpu_baseline": cpu, "mixed_vs_fp64": tts}
 
 
-def run_counters(args):
-    """Short run for rocprofv3 --pmc: reference copy of known size, then a capped solve."""
-    import torch
+def _workload_operator(name, args, dev):
+    """(workload, system, operator precision, nrhs, solve tolerance) of a single-system workload."""
     import workloads as wl
+    if name == "c4":
+        w = wl.config4()
+        return w, w.systems[0], args.prec or "fp32", 8, 1e-6
+    if name == "c5":
+        w = wl.config5()
+        return w, w.systems[0], args.prec or "bf16", 16, 1e-6
+    w = wl.config2(m=args.m, nrhs=args.nrhs)
+    return w, w.systems[0], "fp32", args.nrhs, args.tol
+
+
+def run_counters(args):
+    """Short run for rocprofv3 --pmc, in the benchmark's launch configuration.
+
+    Order of GPU work: operator set-up and the tile autotuner, then a 256 MiB
+    device-to-device copy (the reference for the HBM byte counters, and the
+    marker after which dispatches belong to the solve), then one solve capped
+    at --max-iters iterations (no right-hand side converges that early).
+    """
+    import torch
     from paper_2309_03060_amd import KronOperator, SystemSpec
     dev = torch.device("cuda:0")
-    a = torch.ones(64 << 20, dtype=torch.float32, device=dev)    # 256 MiB
-    b = torch.empty_like(a)
-    b.copy_(a)
-    torch.cuda.synchronize()
-    w = wl.config2(m=args.m, nrhs=args.nrhs)
-    s = w.systems[0]
-    spec = SystemSpec(factors=[[torch.tensor(f, device=dev) for f in s.factors[0]]], sigma2=s.sigma2)
-    op = KronOperator([spec], prec="fp32")
+    name = args.workload if args.workload in ("c4", "c5") else "c2"
+    w, s, prec, nrhs, tol = _workload_operator(name, args, dev)
+    spec = SystemSpec(factors=[[torch.tensor(f, device=dev) for f in row] for row in s.factors], sigma2=s.sigma2,
+                      diag=None if s.diag is None else torch.tensor(s.diag, device=dev))
+    op = KronOperator([spec], prec=prec)
     B = torch.tensor(w.B[0], device=dev).reshape(-1).contiguous()
-    op.solve(B, args.nrhs, tol=args.tol, max_iters=args.max_iters, prec="fp32", inner_tol=0.1, check_every=0)
+    if args.autotune:
+        op.autotune(nrhs)
+    a = torch.ones(COPY_REF_WORDS, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    torch.mul(a, 1.0, out=b)          # elementwise kernel: 16-byte loads / stores per lane, like ours
+    torch.cuda.synchronize()
+    b.copy_(a)                        # runtime copy kernel: the marker that ends the set-up phase
+    torch.cuda.synchronize()
+    iters = args.max_iters or 48
+    op.solve(B, nrhs, tol=tol, max_iters=iters, prec=prec, inner_tol=0.1, check_every=0)
     torch.cuda.synchronize()
     op.close()
-    print(json.dumps({"counters_run": "done", "copy_bytes": 2 * (64 << 20) * 4, "max_iters": args.max_iters}))
+    print(json.dumps({"counters_run": name, "prec": prec, "copy_bytes": 2 * COPY_REF_WORDS * 4, "max_iters": iters}))
+
+
+# --- rocprofv3 counter summaries ---------------------------------------------------------------
+COPY_REF_WORDS = 64 << 20            # the counters run's reference copy: 256 MiB read + 256 MiB written
+PMC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+KERNEL_SOURCES = {                   # files each launch class is compiled from (counters go stale with them)
+    "contract": ["contract.hip", "contract.h", "common.h"],
+    "slab23": ["slab.hip", "slab.h", "common.h"],
+    "update": ["vector.hip", "vector.h", "common.h"],
+}
+# bench launch-class name of each counter class, per workload (c2 fuses modes 2 and 3 in the slab pass,
+# so its only column-layout FP32 contraction is the last mode)
+BENCH_CLASS = {"c2": {"contract_cols_f32": "contract_last", "slab23_f32": "slab23", "update_float": "update"}}
+
+
+def kernel_class(name):
+    """Launch class of a demangled kernel name from a rocprofv3 trace."""
+    import re
+    m = re.search(r"k_contract<cola::Pol(\w+), \d+, \d+, (true|false)>", name)
+    if m:
+        return f"contract_{'rows' if m.group(2) == 'true' else 'cols'}_{m.group(1).lower()}"
+    m = re.search(r"k_slab23<cola::Slab(\w+)[,>]", name)
+    if m:
+        return f"slab23_{m.group(1).lower()}"
+    m = re.search(r"k_cg_update<(\w+)", name)
+    if m:
+        return f"update_{m.group(1)}"
+    m = re.search(r"cola::(k_\w+)", name)
+    return m.group(1) if m else "other"
+
+
+def sources_digest(kind):
+    import hashlib
+    h = hashlib.sha1()
+    for f in KERNEL_SOURCES[kind]:
+        with open(os.path.join(ROOT, "paper_2309_03060_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def pmc_summary(csvs, workload, out_json):
+    """Per launch class averages of the counters in rocprofv3 --pmc CSV files (one file per pass).
+
+    Dispatches before the 256 MiB reference copy (operator set-up, autotuner) are dropped.  The
+    byte counters are scaled so that the reference copy reads and writes exactly its size.
+    Prints a markdown table; merges the traffic record of this workload into out_json.
+    """
+    import collections
+    import csv
+    per = collections.defaultdict(lambda: collections.defaultdict(list))
+    dur = collections.defaultdict(list)
+    ref, ref_copy = {}, {}
+    for path in csvs:
+        rows = list(csv.DictReader(open(path)))
+        marker = None
+        for r in rows:
+            if "copyBuffer" in r["Kernel_Name"] and int(r["Grid_Size"]) * 1024 * 4 >= COPY_REF_WORDS * 2:
+                marker = int(r["Dispatch_Id"])
+                ref_copy[r["Counter_Name"]] = float(r["Counter_Value"])
+            elif "MulFunctor" in r["Kernel_Name"] and int(r["Grid_Size"]) * 4 * 4 >= COPY_REF_WORDS:
+                ref[r["Counter_Name"]] = float(r["Counter_Value"])
+        if marker is None:
+            raise SystemExit(f"{path}: no reference copy dispatch found")
+        for r in rows:
+            if int(r["Dispatch_Id"]) <= marker:
+                continue
+            c = kernel_class(r["Kernel_Name"])
+            per[c][r["Counter_Name"]].append(float(r["Counter_Value"]))
+            if r["Counter_Name"] in ("FETCH_SIZE", "WRITE_SIZE"):
+                dur[c].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3)
+    copy_kib = COPY_REF_WORDS * 4 / 1024
+    scale = {k: copy_kib / v for k, v in ref.items() if k in ("FETCH_SIZE", "WRITE_SIZE") and v > 0}
+    lines = [f"| class | dispatches | avg us (counter run) | " + " | ".join(
+        sorted({k for d in per.values() for k in d})) + " | HBM MB/launch (scaled) |",
+        "|---|---|---|" + "---|" * len({k for d in per.values() for k in d}) + "---|"]
+    cols = sorted({k for d in per.values() for k in d})
+    record = {}
+    for c in sorted(per):
+        d = per[c]
+        avg = {k: sum(v) / len(v) for k, v in d.items()}
+        mb = None
+        if "FETCH_SIZE" in avg and "WRITE_SIZE" in avg and len(scale) == 2:
+            byt = 1024 * (avg["FETCH_SIZE"] * scale["FETCH_SIZE"] + avg["WRITE_SIZE"] * scale["WRITE_SIZE"])
+            mb = byt / 1e6
+            bench = BENCH_CLASS.get(workload, {}).get(c)
+            if bench:
+                kind = "contract" if c.startswith("contract") else c.split("_")[0]
+                record[bench] = {"bytes_per_launch_all_rhs_active": round(byt),
+                                 "fetch_kib": round(avg["FETCH_SIZE"], 1), "write_kib": round(avg["WRITE_SIZE"], 1),
+                                 "sources_sha1": sources_digest(kind)}
+        n = max(len(v) for v in d.values())
+        du = sum(dur[c]) / len(dur[c]) if dur[c] else float("nan")
+        lines.append(f"| {c} | {n} | {du:.1f} | " + " | ".join(
+            f"{avg[k]:.4g}" if k in avg else "" for k in cols) + f" | {'' if mb is None else f'{mb:.1f}'} |")
+    print("\n".join(lines))
+    for label, d in (("elementwise copy kernel (the scale used)", ref), ("runtime copy kernel", ref_copy)):
+        print(f"\n{label}, 256 MiB read + 256 MiB written: " +
+              ", ".join(f"{k} {v:.1f} KiB -> scale {copy_kib / v:.3f}" for k, v in sorted(d.items())
+                        if k in ("FETCH_SIZE", "WRITE_SIZE")))
+    if out_json and record:
+        data = json.load(open(out_json)) if os.path.exists(out_json) else {}
+        data[workload] = {"scale": scale, "kernels": record}
+        with open(out_json, "w") as fh:
+            json.dump(data, fh, indent=1, sort_keys=True)
+            fh.write("\n")
+
+
+def trace_summary(prefix, cmd, title):
+    """Markdown summary of a rocprofv3 --kernel-trace --stats --output-format csv run."""
+    import csv
+    import statistics
+    stats = list(csv.DictReader(open(f"{prefix}_kernel_stats.csv")))
+    per = {}
+    for r in csv.DictReader(open(f"{prefix}_kernel_trace.csv")):
+        per.setdefault(r["Kernel_Name"], []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3)
+    print(f"# {title}\n\nCommand (repository root on the GPU box, `export TMPDIR=/tmp` first):\n\n    {cmd}\n")
+    print("| class | kernel | calls | avg us | p50 us | p90 us | share of kernel time |")
+    print("|---|---|---|---|---|---|---|")
+    for r in stats[:14]:
+        v = sorted(per.get(r["Name"], [0.0]))
+        p90 = v[min(len(v) - 1, int(0.9 * len(v)))]
+        print(f"| {kernel_class(r['Name'])} | `{r['Name'][:90]}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+              f"{statistics.median(v):.2f} | {p90:.2f} | {float(r['Percentage']):.2f}% |")
+
+
+def measured_traffic(workload, kernel, nrhs, rhs_iters, launches):
+    """HBM bytes per launch from the committed counter record, scaled to the average number of active
+    right-hand sides per launch; None when there is no record or the kernel's sources changed since."""
+    try:
+        rec = json.load(open(PMC_FILE))[workload]["kernels"][kernel]
+    except (OSError, KeyError, ValueError):
+        return None
+    kind = "contract" if kernel.startswith("contract") else kernel
+    if rec.get("sources_sha1") != sources_digest(kind):
+        return None
+    return int(rec["bytes_per_launch_all_rhs_active"] * (rhs_iters / launches) / nrhs)
 
 
 def main():
@@ -301,6 +478,12 @@ def main():
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    if args.pmc_summary:
+        pmc_summary(args.pmc_summary, args.workload, args.pmc_out)
+        return
+    if args.trace_summary:
+        trace_summary(args.trace_summary[0], args.trace_summary[1], args.trace_summary[2])
+        return
     if args.counters:
         run_counters(args)
         return
@@ -324,7 +507,8 @@ def main():
     B = torch.tensor(w.B[0], device=dev).reshape(-1).contiguous()
     if args.autotune:
         op.autotune(nrhs)
-    opts = dict(tol=args.tol, max_iters=20000, prec="fp32", inner_tol=0.1, check_every=32, refine="reliable")
+    opts = dict(tol=args.tol, max_iters=args.max_iters or 20000, prec="fp32", inner_tol=0.1, check_every=32,
+                refine="reliable")
 
     for _ in range(args.warmup):
         op.solve(B, nrhs, **opts)
@@ -362,8 +546,9 @@ def main():
         per_launch = alg_bytes / launches
         avg_s = kern[dom]["total_ms"] * 1e-3 / launches
         achieved = per_launch / avg_s / 1e9
+        traffic = measured_traffic("c2", dom, nrhs, rhs_iters, launches) if args.m == 64 and nrhs == 32 else None
         roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "bytes_per_launch": int(per_launch), "avg_launch_us": round(avg_s * 1e6, 2),
                 "per_kernel": {k: {"avg_us": round(v["avg_us"], 2), "launches": v["launches"],
                                    "GB/s": round(BYTES_PER_ELEM[k] * n * rhs_iters / v["launches"] /
@@ -377,7 +562,8 @@ def main():
         for label, o in (("mixed_fp32_reliable", dict(opts, tol=1e-6)),
                          ("mixed_fp32_restarted", dict(opts, tol=1e-6, refine="restart", inner_tol=1e-4,
                                                        max_sweeps=60)),
-                         ("fp64_cg", dict(tol=1e-6, max_iters=20000, prec="fp64", check_every=32))):
+                         ("fp64_cg", dict(tol=1e-6, max_iters=args.max_iters or 20000, prec="fp64",
+                                          check_every=32))):
             torch.cuda.synchronize()
             t1 = time.perf_counter()
             X, info = op.solve(B, nrhs, **o)
@@ -387,6 +573,7 @@ def main():
             res[label] = {"seconds": round(t, 4), "iters_max": max(r["iters"] for r in rec),
                           "relres_max": max(r["relres"] for r in rec),
                           "status": sorted({r["status"] for r in rec})}
+            progress(f"time-to-solution {label}: {res[label]['seconds']} s")
         res["speedup"] = round(res["fp64_cg"]["seconds"] / res["mixed_fp32_reliable"]["seconds"], 3)
         res["note"] = ("fp64_cg relres is its recursive residual; mixed relres is the FP64 true residual; "
                        "speedup = fp64_cg seconds / mixed_fp32_reliable seconds")

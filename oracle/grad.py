@@ -92,7 +92,7 @@ def grad_kron(terms, X: np.ndarray, Lam: np.ndarray, diag_present: bool = False)
                 T = np.moveaxis(T, 0, m + 1)
             Zk = np.moveaxis(T, k + 1, 1).reshape(nrhs, dims[k], -1)
             Lk = np.moveaxis(Lam.reshape((nrhs,) + dims), k + 1, 1).reshape(nrhs, dims[k], -1)
-            row_j.append(-np.einsum("rap,rip->ai", Lk, Zk))
+            row_j.append(-np.einsum("rap,rip->ai", Lk, Zk, optimize=True))
         dfac.append(row_j)
     dd = -(Lam * X).sum(axis=0) if diag_present else None
     dsigma2 = float(-(Lam * X).sum())
