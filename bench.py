@@ -242,19 +242,25 @@ def run_single(args, name):
     dt, infos = timed_solves(op, B, nrhs, opts, args.steps, args.warmup, decode_info, nrhs, backward=G)
     rhs_iters, statuses, worst = solve_stats(infos, decode_info, nrhs)
     names = ["slab23", "contract_rows", "contract_mid", "contract_last", "update"]
+    if prec == "fp64":
+        names = [k + "_fp64" for k in names]
     kern = kernel_table(op, names)
+    resid64 = kernel_table(op, ["slab23_fp64", "contract_rows_fp64", "contract_mid_fp64", "contract_last_fp64"]) \
+        if prec != "fp64" else {}
     op.profile_enable(False)
     n = s.n
     # algorithmic FLOPs of one RHS*iteration of the working-precision MVM (Table 2 cost, per mode)
     flop_rhs_it = 2.0 * n * sum(sum(f.shape[0] for f in row) for row in s.factors)
     per_kernel = {k: {"avg_us": round(v["avg_us"], 2), "launches": v["launches"]} for k, v in kern.items()}
-    contract_ms = sum(v["total_ms"] for k, v in kern.items() if k != "update")
+    contract_ms = sum(v["total_ms"] for k, v in kern.items() if not k.startswith("update"))
     roof = None
     if contract_ms > 0:
         ach = flop_rhs_it * rhs_iters / (contract_ms * 1e-3) / 1e12
         peak = {"fp32": FP32_MFMA_PEAK_TFLOPS, "bf16": 2500.0, "bf16x3": 2500.0, "fp64": 78.6}[prec]
         roof = {"kernel": "contraction passes (all modes)", "bound": "mfma", "achieved": round(ach, 2), "peak": peak,
                 "unit": "TFLOP/s", "frac": round(ach / peak, 4), "traffic": None, "per_kernel": per_kernel,
+                "fp64_residual_passes": {k: {"avg_us": round(v["avg_us"], 2), "launches": v["launches"]}
+                                         for k, v in resid64.items()},
                 "note": "bf16x3 issues 6 bf16 products per useful one; its frac is against the bf16 peak"}
     tts = None
     if not args.no_tts and prec != "fp64":
@@ -331,10 +337,14 @@ def run_counters(args):
     b.copy_(a)                        # runtime copy kernel: the marker that ends the set-up phase
     torch.cuda.synchronize()
     iters = args.max_iters or 48
-    op.solve(B, nrhs, tol=tol, max_iters=iters, prec=prec, inner_tol=0.1, check_every=0)
+    # inner_tol 1e-30: no reliable update falls due this early, so every launch has all RHS active
+    _, info = op.solve(B, nrhs, tol=tol, max_iters=iters, prec=prec, inner_tol=1e-30, check_every=0)
     torch.cuda.synchronize()
+    from paper_2309_03060_amd import decode_info
+    rhs_iters = sum(r["iters"] for r in decode_info(info, nrhs))
     op.close()
-    print(json.dumps({"counters_run": name, "prec": prec, "copy_bytes": 2 * COPY_REF_WORDS * 4, "max_iters": iters}))
+    print(json.dumps({"counters_run": name, "prec": prec, "copy_bytes": 2 * COPY_REF_WORDS * 4, "max_iters": iters,
+                      "rhs_iters": rhs_iters, "all_rhs_active_every_iteration": rhs_iters == iters * nrhs}))
 
 
 # --- rocprofv3 counter summaries ---------------------------------------------------------------
@@ -389,15 +399,17 @@ def pmc_summary(csvs, workload, out_json):
     ref, ref_copy = {}, {}
     for path in csvs:
         rows = list(csv.DictReader(open(path)))
-        marker = None
-        for r in rows:
-            if "copyBuffer" in r["Kernel_Name"] and int(r["Grid_Size"]) * 1024 * 4 >= COPY_REF_WORDS * 2:
-                marker = int(r["Dispatch_Id"])
-                ref_copy[r["Counter_Name"]] = float(r["Counter_Value"])
-            elif "MulFunctor" in r["Kernel_Name"] and int(r["Grid_Size"]) * 4 * 4 >= COPY_REF_WORDS:
-                ref[r["Counter_Name"]] = float(r["Counter_Value"])
-        if marker is None:
+        # the elementwise reference is the last multiply kernel; the runtime copy right after it
+        # is the second reference and the marker
+        muls = [r for r in rows if "MulFunctor" in r["Kernel_Name"]]
+        if not muls:
             raise SystemExit(f"{path}: no reference copy dispatch found")
+        mul_id = int(muls[-1]["Dispatch_Id"])
+        ref[muls[-1]["Counter_Name"]] = float(muls[-1]["Counter_Value"])
+        copies = [r for r in rows if "copyBuffer" in r["Kernel_Name"] and int(r["Dispatch_Id"]) > mul_id]
+        marker = int(copies[0]["Dispatch_Id"]) if copies else mul_id
+        if copies:
+            ref_copy[copies[0]["Counter_Name"]] = float(copies[0]["Counter_Value"])
         for r in rows:
             if int(r["Dispatch_Id"]) <= marker:
                 continue
@@ -535,6 +547,7 @@ def main():
         ms, cnt = op.profile_read(name)
         if cnt:
             kern[name] = {"total_ms": ms, "launches": cnt, "avg_us": 1e3 * ms / cnt}
+    resid64 = kernel_table(op, ["slab23_fp64", "contract_last_fp64"])
     op.profile_enable(False)
     dom = max(kern, key=lambda k: kern[k]["total_ms"]) if kern else None
     roof = None
@@ -553,7 +566,9 @@ def main():
                 "per_kernel": {k: {"avg_us": round(v["avg_us"], 2), "launches": v["launches"],
                                    "GB/s": round(BYTES_PER_ELEM[k] * n * rhs_iters / v["launches"] /
                                                  (v["avg_us"] * 1e-6) / 1e9, 1)}
-                               for k, v in kern.items()}}
+                               for k, v in kern.items()},
+                "fp64_residual_passes": {k: {"avg_us": round(v["avg_us"], 2), "launches": v["launches"]}
+                                         for k, v in resid64.items()}}
 
     # mixed precision vs plain FP64 at 1e-6 true relative residual
     tts = None

@@ -177,8 +177,13 @@ int32_t cola_cg_solve_backward(cola_op_t op, const double* X, const double* G, i
 int32_t cola_autotune(cola_op_t op, int32_t nrhs, void* stream);
 
 /* Per-kernel timing with HIP events recorded on the launch stream around
- * every kernel of the named class ("contract", "contract_last", "update",
- * "resident", ...).  enable != 0 starts collecting (and clears totals). */
+ * every kernel of the named class.  Classes: "slab23" (fused modes 2-3 of
+ * three-mode terms), "contract_rows" (last mode), "contract_mid" (middle
+ * mode), "contract_last" (first mode, with the diagonal term and the CG
+ * epilogue), "update" (x, r update and residual norm), "resident" (batched
+ * small systems); the same names with "_fp64" for launches in FP64 (plain
+ * FP64 solves and the FP64 residuals of mixed precision).  enable != 0
+ * starts collecting (and clears totals). */
 int32_t cola_profile_enable(cola_op_t op, int32_t enable);
 /* Totals since enable: summed milliseconds and launch count for `kernel`;
  * synchronises the device.  Unknown names report zero launches. */

@@ -170,7 +170,7 @@ int32_t enqueue_mvm(cola_op_s* op, const SysInfo& s, int prec, int nrhs, const v
         sa.gate_stride = tmpl.gate_stride;
         sa.cg = tmpl.cg;
         {
-            ProfScope ps(op->prof, "slab23", st);
+            ProfScope ps(op->prof, prec == COLA_PREC_FP64 ? "slab23_fp64" : "slab23", st);
             HIP_TRY(launch_slab23(prec, sa, st));
         }
         in = op->ws.inter[0];
@@ -210,14 +210,15 @@ int32_t enqueue_mvm(cola_op_s* op, const SysInfo& s, int prec, int nrhs, const v
             a.y_tstride = 0;
             a.dvec = diag;
             a.sigma2 = s.sigma2;
-            kname = "contract_last";
+            kname = prec == COLA_PREC_FP64 ? "contract_last_fp64" : "contract_last";
         } else {
             a.nsum = 1;
             a.nout = s.J;
             a.Y = op->ws.inter[buf];
             a.y_tstride = tstride;
             a.epi = EPI_STORE;
-            kname = rows ? "contract_rows" : "contract_mid";
+            kname = prec == COLA_PREC_FP64 ? (rows ? "contract_rows_fp64" : "contract_mid_fp64")
+                                           : (rows ? "contract_rows" : "contract_mid");
         }
         TileCfg cfg = tile_for(op, prec, rows, nk, a.B, a.a_per_rhs);
         {
@@ -266,7 +267,7 @@ int32_t enqueue_iteration(cola_op_s* op, const SysInfo& s, int prec, int nrhs, T
     a.Epout = p;
     int32_t rc = enqueue_mvm(op, s, prec, nrhs, p, r, q, a, st);
     if (rc != COLA_OK) return rc;
-    ProfScope ps(op->prof, "update", st);
+    ProfScope ps(op->prof, sizeof(T) == 8 ? "update_fp64" : "update", st);
     HIP_TRY(cg_update<T>(x, r, p, q, s.n, nrhs, w.cg, w.partials, (int)w.part_stride, w.counters, w.cnt, st));
     return COLA_OK;
 }
