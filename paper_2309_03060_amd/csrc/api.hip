@@ -10,6 +10,7 @@
 #include <cstring>
 #include <new>
 
+#include "gemm.h"
 #include "grad.h"
 #include "op.h"
 #include "resident.h"
@@ -143,6 +144,49 @@ int32_t enqueue_mvm(cola_op_s* op, const SysInfo& s, int prec, int nrhs, const v
     if (s.diag_off >= 0)
         diag = (prec == COLA_PREC_FP64) ? (const void*)(op->diag64 + s.diag_off)
                                         : (const void*)(op->diag32 + s.diag_off);
+    if (op->use_gemm2 && (tmpl.epi == EPI_CG || tmpl.epi == EPI_MATVEC) && gemm2_supported(prec, s.Fv, s.dims)) {
+        // large two-mode operator in BF16: both mode products as dense GEMMs
+        Gemm2Args g;
+        std::memset(&g, 0, sizeof(g));
+        g.n1 = (int32_t)s.dims[0];
+        g.n2 = (int32_t)s.dims[1];
+        g.J = s.J;
+        g.nrhs = nrhs;
+        g.U = op->facbf + s.fac_off[0];
+        g.V = op->facbf + s.fac_off[1];
+        g.X = (const float*)X;
+        g.R = (const float*)Rpnew;
+        g.P = tmpl.epi == EPI_CG ? (float*)tmpl.Epout : nullptr;
+        g.P16 = (__bf16*)op->ws.inter[1];
+        g.T = (__bf16*)op->ws.inter[0];
+        g.Y = (float*)Yout;
+        g.dvec = (const float*)diag;
+        g.sigma2 = s.sigma2;
+        g.epi = tmpl.epi;
+        g.cg = tmpl.cg;
+        g.gate = tmpl.gate;
+        g.gate_stride = tmpl.gate_stride;
+        g.partials = tmpl.partials;
+        g.part_stride = tmpl.part_stride;
+        g.counters = tmpl.counters;
+        g.cnt = tmpl.cnt;
+        auto al16 = [](const void* q) { return ((uintptr_t)q & 15) == 0; };
+        if (al16(g.U) && al16(g.V) && al16(g.X) && al16(g.R) && al16(g.P) && al16(g.Y) && al16(g.dvec)) {
+            {
+                ProfScope ps(op->prof, "gemm_pack", st);
+                HIP_TRY(launch_gemm2(g, 0, st));
+            }
+            {
+                ProfScope ps(op->prof, "gemm_mode2", st);
+                HIP_TRY(launch_gemm2(g, 1, st));
+            }
+            {
+                ProfScope ps(op->prof, "gemm_mode1", st);
+                HIP_TRY(launch_gemm2(g, 2, st));
+            }
+            return COLA_OK;
+        }
+    }
     const void* in = X;
     int64_t in_tstride = 0;
     int buf = 0;

@@ -1,0 +1,43 @@
+// Kronecker MVM of large two-mode operators in BF16 as two dense GEMMs (host interface).
+#pragma once
+#include "common.h"
+
+namespace cola {
+
+// A = sum_j U_j (x) V_j + diag(d) + sigma2 I with n1 x n1 factors U_j and
+// n2 x n2 factors V_j, both mode sizes multiples of 256.  One MVM q = A p is
+//   pack : P16 = bf16(p)  (CG: p = r + beta p_old first, written back in FP32)
+//   G1   : T[(r, a'), (j, b)] = sum_b' P16[(r, a'), b'] V_j[b, b']    (all terms at once)
+//   G2   : q_r[a, b] = sum_(j, a') U_j[a, a'] T_r[(j, a'), b] + (sigma2 + d) p_r[a, b]
+// G1 stores T transposed per right-hand side, T_r[b][(j, a')], so both GEMMs
+// read their operands k-contiguous; G2 sums the terms inside its k loop.
+struct Gemm2Args {
+    int32_t n1, n2, J, nrhs;
+    const __bf16* U;          // term j's mode-1 factor at U + j * n1 * n1 (row-major)
+    const __bf16* V;          // term j's mode-2 factor at V + j * n2 * n2
+    const float* X;           // CG: p_old; matvec: x
+    const float* R;           // CG: r; matvec: null
+    float* P;                 // CG: p_new (may alias X); matvec: null
+    __bf16* P16;              // nrhs * n1 * n2
+    __bf16* T;                // nrhs * n2 * J * n1
+    float* Y;                 // q
+    const float* dvec;        // n1 * n2 or null
+    double sigma2;
+    int32_t epi;              // EPI_CG or EPI_MATVEC
+    CgState* cg;
+    const int32_t* gate; int32_t gate_stride;
+    double* partials; int32_t part_stride;
+    uint32_t* counters;
+    SolveCounters* cnt;
+};
+
+bool gemm2_supported(int prec, int Fv, const int64_t* dims);
+
+// Enqueue the three kernels of one MVM.  Each is timed under its own profile
+// class by the caller: `stage` 0 = pack, 1 = G1, 2 = G2.
+hipError_t launch_gemm2(const Gemm2Args& a, int stage, hipStream_t s);
+
+// Blocks per right-hand side of G2 (reduction partials needed).
+int64_t gemm2_blocks_per_rhs(int64_t n1, int64_t n2);
+
+}  // namespace cola

@@ -1,0 +1,337 @@
+// Kronecker MVM of large two-mode operators in BF16 as two dense GEMMs.
+//
+// For A = sum_j U_j (x) V_j (+ diagonal) and X_r = p_r reshaped n1 x n2, the
+// MVM is q_r = sum_j U_j X_r V_j^T: one product per mode, the cost of Table 2.
+// When both modes are large the per-mode products are plain dense GEMMs with
+// inner dimensions of 256 and more, so they are run as such on the BF16
+// matrix cores (v_mfma_f32_32x32x16_bf16, FP32 accumulation):
+//
+//   G1: T[(r, a'), (j, b)] = sum_b' P[(r, a'), b'] V_j[b, b']   (terms side by side in N)
+//   G2: q_r[a, b] = sum_(j, a') U_j[a, a'] T_r[(j, a'), b]      (terms summed inside K)
+//
+// G1 stores T transposed per right-hand side (T_r[b][(j, a')]) so that both
+// GEMMs take their operands k-contiguous.  Block tile 256 x 256, k slice 64,
+// 4 waves each owning 128 x 128 (4 x 4 MFMA tiles); two LDS stages and two
+// register sets keep two k slices in flight while one is multiplied.
+// Block indices are mapped so that each XCD works on a contiguous group of
+// tiles that share operand panels in its L2.
+#include "gemm.h"
+
+#include <algorithm>
+
+#include "contract.h"
+
+namespace cola {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+namespace {
+
+constexpr int BM = 256, BN = 256, KS = 64;
+constexpr int KSP = KS + 8;                      // LDS row pitch (bf16): conflict-free 16-byte reads
+constexpr int kChunks = BM * KS / 8 / kThreads;  // 16-byte chunks of one operand slice per thread
+constexpr int kStage = (BM + BN) * KSP;          // bf16 elements of one LDS stage (A and B slices)
+
+__device__ inline floatx16 mfma32(bf16x8 a, bf16x8 b, floatx16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+
+// Row of accumulator element v of a 32 x 32 MFMA tile held by `lane`; the
+// column is lane % 32.
+__device__ inline int row32(int lane, int v) { return 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3); }
+
+// Tile index with all tiles of one XCD contiguous (blocks go to XCDs round robin).
+__device__ inline int xcd_linear(int b, int T) {
+    return (T % 8 == 0) ? (b % 8) * (T / 8) + b / 8 : b;
+}
+
+// acc += A_tile * B_tile^T over k in [0, nk).  abase(k0) / bbase(k0) give the
+// (block-uniform) address of row 0, column k0 of the A / B tile; rows are lda /
+// ldb elements apart and every row segment is 16-byte aligned.  Each thread
+// loads rows crow + 32 q at one per-thread offset from a uniform base, which
+// keeps the address arithmetic in scalar registers.
+template <class ABase, class BBase>
+__device__ inline void gemm_tile(floatx16 (&acc)[4][4], int nk, ABase abase, int64_t lda, BBase bbase, int64_t ldb,
+                                 __bf16* smem) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int crow = tid >> 3, ck = (tid & 7) * 8;
+    const uint32_t aoff = (uint32_t)(crow * lda + ck), boff = (uint32_t)(crow * ldb + ck);
+    const int klast = nk - KS;
+    auto load = [&](u32x4 (&ra)[kChunks], u32x4 (&rb)[kChunks], int k0) {
+        k0 = k0 < klast ? k0 : klast;                      // clamped, so the loads are unconditional
+        const __bf16* a0 = abase(k0);
+        const __bf16* b0 = bbase(k0);
+#pragma unroll
+        for (int q = 0; q < kChunks; ++q) {
+            ra[q] = *(const u32x4*)(a0 + (int64_t)q * 32 * lda + aoff);
+            rb[q] = *(const u32x4*)(b0 + (int64_t)q * 32 * ldb + boff);
+        }
+    };
+    auto stage = [&](const u32x4 (&ra)[kChunks], const u32x4 (&rb)[kChunks], int buf) {
+        __bf16* As = smem + buf * kStage;
+        __bf16* Bs = As + BM * KSP;
+#pragma unroll
+        for (int q = 0; q < kChunks; ++q) {
+            *(u32x4*)&As[(crow + 32 * q) * KSP + ck] = ra[q];
+            *(u32x4*)&Bs[(crow + 32 * q) * KSP + ck] = rb[q];
+        }
+    };
+    auto frags = [&](bf16x8 (&av)[4], bf16x8 (&bv)[4], const __bf16* As, const __bf16* Bs, int kk) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            av[i] = *(const bf16x8*)&As[(wm * 128 + i * 32 + (lane & 31)) * KSP + kk + 8 * (lane >> 5)];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            bv[j] = *(const bf16x8*)&Bs[(wn * 128 + j * 32 + (lane & 31)) * KSP + kk + 8 * (lane >> 5)];
+    };
+    auto mma16 = [&](const bf16x8 (&av)[4], const bf16x8 (&bv)[4]) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] = mfma32(av[i], bv[j], acc[i][j]);
+    };
+    // one k slice from LDS stage `buf`: the fragments of step kk + 16 are read
+    // while the MFMAs of step kk run
+    auto compute = [&](int buf) {
+        const __bf16* As = smem + buf * kStage;
+        const __bf16* Bs = As + BM * KSP;
+        bf16x8 a0[4], b0[4], a1[4], b1[4];
+        frags(a0, b0, As, Bs, 0);
+        frags(a1, b1, As, Bs, 16);
+        mma16(a0, b0);
+        frags(a0, b0, As, Bs, 32);
+        mma16(a1, b1);
+        frags(a1, b1, As, Bs, 48);
+        mma16(a0, b0);
+        mma16(a1, b1);
+    };
+    // Two LDS stages and two register sets: while slice s is multiplied from
+    // LDS, slice s + 1 (already in registers) is written to the other stage and
+    // slice s + 2 is in flight from memory.  nk is a multiple of 2 KS.
+    u32x4 ra0[kChunks], rb0[kChunks], ra1[kChunks], rb1[kChunks];
+    load(ra0, rb0, 0);
+    load(ra1, rb1, KS);
+    stage(ra0, rb0, 0);
+    __syncthreads();
+    for (int k0 = 0; k0 < nk; k0 += 2 * KS) {
+        load(ra0, rb0, k0 + 2 * KS);
+        __builtin_amdgcn_sched_barrier(0);                 // keep the loads ahead of the MFMAs
+        compute(0);
+        stage(ra1, rb1, 1);
+        __syncthreads();
+        load(ra1, rb1, k0 + 3 * KS);
+        __builtin_amdgcn_sched_barrier(0);
+        compute(1);
+        if (k0 + 2 * KS < nk) stage(ra0, rb0, 0);
+        __syncthreads();
+    }
+}
+
+__device__ inline bool rhs_active(const Gemm2Args& a, int r) {
+    return a.gate ? a.gate[(int64_t)r * a.gate_stride] != 0 : true;
+}
+
+// P16 = bf16(p) with p = r + beta p_old written back in FP32 (CG), or bf16(x).
+template <bool CG>
+__global__ __launch_bounds__(kThreads) void k_gemm2_pack(Gemm2Args a) {
+    const int r = blockIdx.y;
+    if (!rhs_active(a, r)) return;
+    const int64_t n = (int64_t)a.n1 * a.n2;
+    const double beta = CG ? a.cg[r].beta : 0.0;
+    const float* X = a.X + (int64_t)r * n;
+    const float* R = CG ? a.R + (int64_t)r * n : nullptr;
+    float* P = CG ? a.P + (int64_t)r * n : nullptr;
+    __bf16* P16 = a.P16 + (int64_t)r * n;
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n / 8; i += (int64_t)gridDim.x * kThreads) {
+        const int64_t e = i * 8;
+        floatx4 x0 = *(const floatx4*)(X + e), x1 = *(const floatx4*)(X + e + 4);
+        if constexpr (CG) {
+            const floatx4 r0 = *(const floatx4*)(R + e), r1 = *(const floatx4*)(R + e + 4);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                x0[c] = pnew_of(r0[c], x0[c], beta);
+                x1[c] = pnew_of(r1[c], x1[c], beta);
+            }
+            *(floatx4*)(P + e) = x0;
+            *(floatx4*)(P + e + 4) = x1;
+        }
+        bf16x8 h;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            h[c] = (__bf16)x0[c];                          // round to nearest even
+            h[c + 4] = (__bf16)x1[c];
+        }
+        *(bf16x8*)(P16 + e) = h;
+    }
+}
+
+// G1: T_r[b][j n1 + a'] = sum_b' P16[r n1 + a', b'] V_j[b, b'].
+__global__ __launch_bounds__(kThreads) void k_gemm2_t(Gemm2Args a) {
+    __shared__ __attribute__((aligned(16))) __bf16 smem[2 * kStage];
+    const int Mt = a.nrhs * (a.n1 / BM), Nt = a.J * (a.n2 / BN);
+    const int L = xcd_linear(blockIdx.x, Mt * Nt);
+    int mt, nt;
+    if (Mt % 4 == 0 && Nt % 8 == 0) {                      // 4 x 8 groups of tiles share A and B panels
+        const int s = L / 32, w = L % 32, sn = Nt / 8;
+        mt = (s / sn) * 4 + w / 8;
+        nt = (s % sn) * 8 + w % 8;
+    } else {
+        mt = L / Nt;
+        nt = L % Nt;
+    }
+    const int64_t m0 = (int64_t)mt * BM;
+    const int r = (int)(m0 / a.n1), a0 = (int)(m0 % a.n1);
+    if (!rhs_active(a, r)) return;
+    const int n0 = nt * BN;
+    const int j = n0 / a.n2, b0 = n0 % a.n2;
+    const int64_t n2 = a.n2;
+    const __bf16* Ab = a.P16 + m0 * n2;
+    const __bf16* Bb = a.V + (int64_t)n0 * n2;
+    floatx16 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) acc[i][jj] = floatx16{};
+    gemm_tile(acc, a.n2, [&](int k0) { return Ab + k0; }, n2, [&](int k0) { return Bb + k0; }, n2, smem);
+
+    // transposed bf16 store, one 32-column slice of the wave's sub-tile at a
+    // time: FP32 staged in LDS as [column][row], then 8 rows per 16-byte store
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, wm = wave >> 1, wn = wave & 1;
+    const int64_t ldt = (int64_t)a.J * a.n1;
+    __bf16* Tb = a.T + ((int64_t)r * a.n2 + b0 + wn * 128) * ldt + (int64_t)j * a.n1 + a0 + wm * 128;
+    constexpr int TP = 128 + 4;                            // staging pitch (floats)
+    float* Ef = (float*)smem + wave * 32 * TP;             // [32 columns][128 rows]
+#pragma unroll
+    for (int jt = 0; jt < 4; ++jt) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) Ef[(lane & 31) * TP + i * 32 + row32(lane, v)] = acc[i][jt][v];
+        __syncthreads();
+#pragma unroll 2
+        for (int c = 0; c < 8; ++c) {
+            const int id = lane + 64 * c;
+            const int col = id >> 4, m8 = (id & 15) * 8;
+            const floatx4 lo = *(const floatx4*)&Ef[col * TP + m8];
+            const floatx4 hi = *(const floatx4*)&Ef[col * TP + m8 + 4];
+            bf16x8 h;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                h[u] = (__bf16)lo[u];                      // round to nearest even
+                h[u + 4] = (__bf16)hi[u];
+            }
+            *(bf16x8*)(Tb + (int64_t)(jt * 32 + col) * ldt + m8) = h;
+        }
+        __syncthreads();
+    }
+}
+
+// G2: q_r[a, b] = sum_(j, a') U_j[a, a'] T_r[b][j n1 + a'] + (sigma2 + d) p_r[a, b],
+// with the CG epilogue's partial p.q and the step length alpha.
+__global__ __launch_bounds__(kThreads) void k_gemm2_y(Gemm2Args a) {
+    __shared__ __attribute__((aligned(16))) __bf16 smem[2 * kStage];
+    __shared__ double red[4];
+    const int tn = a.n2 / BN, tpr = (a.n1 / BM) * tn;
+    const int L = xcd_linear(blockIdx.x, a.nrhs * tpr);
+    const int r = L / tpr, t = L % tpr;
+    if (!rhs_active(a, r)) return;
+    const int a0 = (t / tn) * BM, b0 = (t % tn) * BN;
+    const int64_t n1 = a.n1, ldt = (int64_t)a.J * a.n1;
+    const __bf16* Tr = a.T + ((int64_t)r * a.n2 + b0) * ldt;
+    floatx16 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) acc[i][jj] = floatx16{};
+    gemm_tile(acc, (int)ldt,
+              [&](int k0) {
+                  const int64_t j = k0 / n1;               // a 64-wide k slice never spans two terms
+                  return a.U + j * n1 * n1 + a0 * n1 + (k0 - j * n1);
+              },
+              n1, [&](int k0) { return Tr + k0; }, ldt, smem);
+
+    // epilogue, one 32-column slice of the wave's sub-tile at a time, staged in
+    // LDS so that p, d and q move as 16-byte vectors along rows
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, wm = wave >> 1, wn = wave & 1;
+    const int64_t n = n1 * a.n2;
+    const bool cg = a.epi == EPI_CG;
+    const float* Pr = (cg ? a.P : a.X) + (int64_t)r * n;
+    float* Yr = a.Y + (int64_t)r * n;
+    const float s2 = (float)a.sigma2;
+    constexpr int FP = 32 + 4;                             // staging pitch (floats)
+    float* Ef = (float*)smem + wave * 128 * FP;            // [128 rows][32 columns]
+    double dot = 0.0;
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) Ef[(i * 32 + row32(lane, v)) * FP + (lane & 31)] = acc[i][jj][v];
+        __syncthreads();
+#pragma unroll 4
+        for (int c = 0; c < 16; ++c) {
+            const int id = lane + 64 * c;
+            const int row = id >> 3, c4 = (id & 7) * 4;
+            const int64_t e = (int64_t)(a0 + wm * 128 + row) * a.n2 + b0 + wn * 128 + jj * 32 + c4;
+            const floatx4 y = *(const floatx4*)&Ef[row * FP + c4];
+            const floatx4 p = *(const floatx4*)(Pr + e);
+            floatx4 dg = floatx4{s2, s2, s2, s2};
+            if (a.dvec) dg += *(const floatx4*)(a.dvec + e);
+            floatx4 q;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                q[u] = y[u] + dg[u] * p[u];
+                dot += (double)p[u] * (double)q[u];
+            }
+            *(floatx4*)(Yr + e) = q;
+        }
+        __syncthreads();
+    }
+    if (!cg) return;
+    const double s = block_sum(dot, red);
+    double tot;
+    if (last_block_reduce(s, a.partials + (int64_t)r * a.part_stride, a.counters + r, tpr, t, &tot, red) &&
+        threadIdx.x == 0) {
+        CgState& st = a.cg[r];
+        if (!(tot > 0.0) || !finite_d(tot)) {
+            st.status = finite_d(tot) ? COLA_ERR_NOT_SPD : COLA_ERR_NONFINITE;
+            st.active = 0;
+            atomicSub(&a.cnt->num_active, 1);
+        } else {
+            st.alpha = st.rho / tot;
+        }
+    }
+}
+
+}  // namespace
+
+bool gemm2_supported(int prec, int Fv, const int64_t* dims) {
+    return prec == COLA_PREC_BF16 && Fv == 2 && dims[0] >= BM && dims[1] >= BN && dims[0] % BM == 0 &&
+           dims[1] % BN == 0;
+}
+
+int64_t gemm2_blocks_per_rhs(int64_t n1, int64_t n2) { return (n1 / BM) * (n2 / BN); }
+
+hipError_t launch_gemm2(const Gemm2Args& a, int stage, hipStream_t s) {
+    if (a.n1 % BM || a.n2 % BN || a.n1 < BM || a.n2 < BN || a.nrhs < 1 || a.J < 1) return hipErrorInvalidValue;
+    const bool cg = a.epi == EPI_CG;
+    if (cg && (!a.R || !a.P || !a.cg)) return hipErrorInvalidValue;
+    if (stage == 0) {
+        const int64_t n8 = (int64_t)a.n1 * a.n2 / 8;
+        const int64_t bx = std::min<int64_t>(512, (n8 + kThreads - 1) / kThreads);
+        dim3 grid((unsigned)bx, (unsigned)a.nrhs);
+        if (cg) hipLaunchKernelGGL(k_gemm2_pack<true>, grid, dim3(kThreads), 0, s, a);
+        else hipLaunchKernelGGL(k_gemm2_pack<false>, grid, dim3(kThreads), 0, s, a);
+    } else if (stage == 1) {
+        const int64_t T = (int64_t)a.nrhs * (a.n1 / BM) * a.J * (a.n2 / BN);
+        hipLaunchKernelGGL(k_gemm2_t, dim3((unsigned)T), dim3(kThreads), 0, s, a);
+    } else {
+        const int64_t T = (int64_t)a.nrhs * gemm2_blocks_per_rhs(a.n1, a.n2);
+        hipLaunchKernelGGL(k_gemm2_y, dim3((unsigned)T), dim3(kThreads), 0, s, a);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace cola

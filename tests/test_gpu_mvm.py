@@ -97,3 +97,51 @@ def test_matvec_full_size_c2_sampled():
             assert abs(Y64[r, idx] - ref) <= 1e-13 * scale
             assert abs(Y32[r, idx] - ref) <= 3e-6 * scale
     op.close()
+
+
+# Two-mode operators whose modes are multiples of 256 run their BF16 MVM as two
+# dense GEMMs (pack, mode-2 GEMM over all terms, mode-1 GEMM summing the terms).
+GEMM_SHAPES = [((256, 256), 1, False, 1), ((256, 512), 3, True, 3), ((512, 256), 2, True, 2)]
+
+
+@pytest.mark.parametrize("shape,nterms,diag,nrhs", GEMM_SHAPES)
+def test_matvec_bf16_dense_gemm_path(shape, nterms, diag, nrhs):
+    import torch
+    from gpu_util import make_op, pack, unpack
+    s = _systems(shape, nterms, diag, seed=3)
+    X = np.random.default_rng(4).standard_normal((nrhs, s.n))
+    op = make_op([s], prec="bf16")
+    Y = unpack(op.matvec(pack([X], torch.float32), nrhs), [s], nrhs)[0]
+    Xr = lowprec.to_fp32(X)
+    ref = kron.mvm(s.factors, Xr, s.sigma2, s.diag)
+    absref = kron.mvm([[np.abs(f) for f in row] for row in s.factors], np.abs(Xr), abs(s.sigma2),
+                      None if s.diag is None else np.abs(s.diag))
+    # BF16 operands and a BF16 intermediate: about four roundings of 2^-9 each
+    err = (np.abs(Y - ref) / absref).max()
+    assert err <= 2e-2, err
+    # the same operator through the FP64 passes, for a tight structural check
+    Y64 = unpack(op.matvec(pack([X]), nrhs, prec="fp64"), [s], nrhs)[0]
+    assert np.abs(Y64 - kron.mvm(s.factors, X, s.sigma2, s.diag)).max() <= 1e-13 * np.abs(absref).max()
+    op.close()
+
+
+def test_matvec_bf16_gemm_path_after_unaligned_system():
+    """A GEMM-shaped system packed after a small one (its vectors are not 16-byte aligned) still
+    gives the right product (the contraction passes take over)."""
+    import torch
+    from gpu_util import make_op, pack, unpack
+    rng = np.random.default_rng(6)
+    systems = [wl.random_system(rng, (3, 5), nterms=1, diag=False, sigma2=0.2),
+               wl.random_system(rng, (256, 256), nterms=2, diag=True, sigma2=0.1),
+               wl.random_system(rng, (256, 256), nterms=1, diag=False, sigma2=0.3)]
+    nrhs = 1
+    Xs = [rng.standard_normal((nrhs, s.n)) for s in systems]
+    op = make_op(systems, prec="bf16")
+    Ys = unpack(op.matvec(pack(Xs, torch.float32), nrhs), systems, nrhs)
+    for s, X, Y in zip(systems, Xs, Ys):
+        Xr = lowprec.to_fp32(X)
+        ref = kron.mvm(s.factors, Xr, s.sigma2, s.diag)
+        absref = kron.mvm([[np.abs(f) for f in row] for row in s.factors], np.abs(Xr), abs(s.sigma2),
+                          None if s.diag is None else np.abs(s.diag))
+        assert (np.abs(Y - ref) / absref).max() <= 2e-2
+    op.close()

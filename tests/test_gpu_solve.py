@@ -69,6 +69,19 @@ def test_refined_sum_of_kron_with_diag_bf16():
     assert np.linalg.norm(X - xref) <= 1e-4 * np.linalg.norm(xref)
 
 
+def test_refined_bf16_dense_gemm_path():
+    """Sum of two 256^2 Wishart Kronecker terms + diagonal: BF16 CG on the dense-GEMM MVM with FP64
+    reliable updates reaches 1e-6 true residual, certified by the oracle."""
+    w = wl.config5(m=256, nterms=2, nrhs=3)
+    s = w.systems[0]
+    (X,), info = _solve(w.systems, w.B, "bf16", 3, tol=1e-6, max_iters=500, inner_tol=0.1)
+    assert all(i["status"] == 0 for i in info), info
+    rr = kron.relres(s.factors, X, w.B[0], s.sigma2, s.diag)
+    assert np.all(rr <= 1e-6), rr
+    for i, r in zip(info, rr):
+        assert abs(i["relres"] - r) <= 1e-3 * r + 1e-15
+
+
 def test_refined_uneven_batch_fp32():
     w = wl.config3(nsys=6, dmin=5, dmax=40)
     (Xs), info = _solve(w.systems, w.B, "fp32", 1, tol=1e-8, max_iters=3000)
