@@ -71,10 +71,6 @@ __global__ __launch_bounds__(kThreads) void k_slab23(SlabArgs a) {
         K3s[r * KP + c] = (r < n3 && c < n3) ? K3[r * n3 + c] : (V)0;
     }
 
-    auto next_active = [&](int64_t sl) -> int64_t {
-        while (sl < a.nslabs && a.gate && !a.gate[(sl / a.a_per_rhs) * a.gate_stride]) sl += gridDim.x;
-        return sl;
-    };
     // The first product U = P K3^T is done per wave on a 16-row strip of the
     // slab, reading its A operand straight from global memory.  The inner
     // (column) index is permuted so each lane loads 4 consecutive columns at
@@ -106,14 +102,44 @@ __global__ __launch_bounds__(kThreads) void k_slab23(SlabArgs a) {
         }
     };
 
-    int64_t sl = next_active(blockIdx.x);
+    // Slabs are visited in grid-stride order.  The next slab's strip, gate
+    // flag and direction coefficient are all loaded right after the first
+    // product of the current slab, so they arrive while the second product
+    // and the store run; a slab whose right-hand side is gated off is skipped
+    // at the top of the loop (its loads were wasted, which only happens once
+    // right-hand sides start to converge).
+    auto beta_of = [&](int64_t s_) -> double { return PNEW ? a.cg[s_ / a.a_per_rhs].beta : 0.0; };
+    // without a gate the flag is read from any valid address and ignored
+    auto flag_of = [&](int64_t s_) -> int32_t {
+        return *(a.gate ? a.gate + (s_ / a.a_per_rhs) * a.gate_stride : (const int32_t*)a.X);
+    };
+    auto next_active = [&](int64_t s_) -> int64_t {     // gate reads only
+        while (s_ < a.nslabs && a.gate && !a.gate[(s_ / a.a_per_rhs) * a.gate_stride]) s_ += gridDim.x;
+        return s_;
+    };
+    int64_t sl = blockIdx.x;
+    int32_t flag = 0;
+    double be = 0.0;
     __syncthreads();
-    if (sl < a.nslabs) load_strip(sl);
+    if (sl < a.nslabs) {
+        load_strip(sl);
+        flag = flag_of(sl);
+        be = beta_of(sl);
+    }
     while (sl < a.nslabs) {
-        const int64_t nx = next_active(sl + gridDim.x);
+        if (a.gate && !flag) {                     // gated off: find the next active slab first
+            sl = next_active(sl + gridDim.x);
+            if (sl < a.nslabs) {
+                load_strip(sl);
+                flag = 1;
+                be = beta_of(sl);
+            }
+            continue;
+        }
+        const int64_t nx = sl + gridDim.x;
+        const int64_t nxc = nx < a.nslabs ? nx : sl;          // clamped: the loads stay unconditional
         V av[16];
         if constexpr (PNEW) {
-            const double be = a.cg[sl / a.a_per_rhs].beta;
 #pragma unroll
             for (int q = 0; q < 16; ++q) av[q] = pnew_of(rv[q], pv[q], be);
         } else {
@@ -131,7 +157,9 @@ __global__ __launch_bounds__(kThreads) void k_slab23(SlabArgs a) {
             for (int j = 0; j < 4; ++j)
                 acc1[j] = smma(av[st], K3s[(16 * j + lr) * KP + kcol], acc1[j]);
         }
-        load_strip(nx < a.nslabs ? nx : sl);       // next strip in flight during the second product
+        load_strip(nxc);                           // next strip in flight during the second product
+        const int32_t nx_flag = flag_of(nxc);
+        const double nx_be = beta_of(nxc);
 #pragma unroll
         for (int j = 0; j < 4; ++j)
 #pragma unroll
@@ -184,6 +212,8 @@ __global__ __launch_bounds__(kThreads) void k_slab23(SlabArgs a) {
         }
         __syncthreads();                           // T read out of U before the next slab writes U
         sl = nx;
+        flag = nx_flag;
+        be = nx_be;
     }
 }
 
