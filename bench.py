@@ -241,8 +241,8 @@ def run_single(args, name):
     G = torch.tensor(w.W[0], device=dev).reshape(-1).contiguous() if (name == "c5" and w.W) else None
     dt, infos = timed_solves(op, B, nrhs, opts, args.steps, args.warmup, decode_info, nrhs, backward=G)
     rhs_iters, statuses, worst = solve_stats(infos, decode_info, nrhs)
-    names = ["slab23", "contract_rows", "contract_mid", "contract_last", "gemm_pack", "gemm_mode2", "gemm_mode1",
-             "update"]
+    names = ["slab23", "contract_rows", "contract_mid", "contract_last", "gemm_pack", "gemm_mode3", "gemm_mode2",
+             "gemm_mode1", "update"]
     if prec == "fp64":
         names = [k + "_fp64" for k in names]
     kern = kernel_table(op, names)

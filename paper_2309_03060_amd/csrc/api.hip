@@ -11,6 +11,7 @@
 #include <new>
 
 #include "gemm.h"
+#include "gemm3.h"
 #include "grad.h"
 #include "op.h"
 #include "resident.h"
@@ -183,6 +184,45 @@ int32_t enqueue_mvm(cola_op_s* op, const SysInfo& s, int prec, int nrhs, const v
             {
                 ProfScope ps(op->prof, "gemm_mode1", st);
                 HIP_TRY(launch_gemm2(g, 2, st));
+            }
+            return COLA_OK;
+        }
+    }
+    if (op->use_gemm3 && (tmpl.epi == EPI_CG || tmpl.epi == EPI_MATVEC) &&
+        gemm3_supported(prec, s.Fv, s.J, s.dims)) {
+        // one-term three-mode FP32 operator with 256-wide modes: three dense GEMMs
+        Gemm3Args g;
+        std::memset(&g, 0, sizeof(g));
+        g.n1 = (int32_t)s.dims[0];
+        g.n2 = (int32_t)s.dims[1];
+        g.n3 = (int32_t)s.dims[2];
+        g.nrhs = nrhs;
+        g.K1 = op->fac32 + s.fac_off[0];
+        g.K2 = op->fac32 + s.fac_off[1];
+        g.K3 = op->fac32 + s.fac_off[2];
+        g.X = (const float*)X;
+        g.R = (const float*)Rpnew;
+        g.Z1 = (float*)op->ws.inter[0];
+        g.Z2 = (float*)op->ws.inter[1];
+        g.Y = (float*)Yout;
+        g.dvec = (const float*)diag;
+        g.sigma2 = s.sigma2;
+        g.epi = tmpl.epi;
+        g.cg = tmpl.cg;
+        g.gate = tmpl.gate;
+        g.gate_stride = tmpl.gate_stride;
+        g.partials = tmpl.partials;
+        g.part_stride = tmpl.part_stride;
+        g.counters = tmpl.counters;
+        g.cnt = tmpl.cnt;
+        auto al16 = [](const void* q) { return ((uintptr_t)q & 15) == 0; };
+        const bool in_place_p = tmpl.epi != EPI_CG || tmpl.Epout == X;   // the direction is written over p_old
+        if (in_place_p && al16(g.K1) && al16(g.K2) && al16(g.K3) && al16(g.X) && al16(g.R) && al16(g.Y) &&
+            al16(g.dvec)) {
+            const char* names[3] = {"gemm_mode3", "gemm_mode2", "gemm_mode1"};
+            for (int m = 3; m >= 1; --m) {
+                ProfScope ps(op->prof, names[3 - m], st);
+                HIP_TRY(launch_gemm3(g, m, st));
             }
             return COLA_OK;
         }

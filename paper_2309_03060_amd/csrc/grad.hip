@@ -19,6 +19,7 @@
 #include "grad.h"
 
 #include "gemm.h"
+#include "gemm3.h"
 #include "vector.h"
 
 namespace cola {
@@ -271,7 +272,9 @@ int32_t autotune_op(cola_op_s* op, int nrhs, hipStream_t st) {
     if (op->prec != COLA_PREC_FP64) precs.push_back(op->prec);
     for (const SysInfo& s : op->sys) {
         for (int prec : precs) {
-            if (op->use_gemm2 && gemm2_supported(prec, s.Fv, s.dims)) continue;   // fixed GEMM tiles
+            if ((op->use_gemm2 && gemm2_supported(prec, s.Fv, s.dims)) ||
+                (op->use_gemm3 && gemm3_supported(prec, s.Fv, s.J, s.dims)))
+                continue;                                                         // fixed GEMM tiles
             for (int k = s.Fv - 1; k >= 0; --k) {
                 const int64_t nk = s.dims[k];
                 int64_t lead = 1, trail = 1;

@@ -120,6 +120,7 @@ struct cola_op_s {
     bool graphs_ok = true;          // false after a capture failure: launch directly
     bool use_slab = true;           // fuse modes 2 and 3 of three-mode terms when slabs fit in LDS
     bool use_gemm2 = true;          // BF16 two-mode operators with large modes: dense-GEMM MVM
+    bool use_gemm3 = true;          // FP32 one-term three-mode operators with 256-wide modes: dense-GEMM MVM
     bool resident_ok = false;       // every system fits the resident batched kernel
     bool use_resident = true;
     int num_cus = 0;

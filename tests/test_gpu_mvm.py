@@ -145,3 +145,23 @@ def test_matvec_bf16_gemm_path_after_unaligned_system():
                           None if s.diag is None else np.abs(s.diag))
         assert (np.abs(Y - ref) / absref).max() <= 2e-2
     op.close()
+
+
+# One-term three-mode operators with 256-wide modes run their FP32 MVM as three
+# dense GEMMs (each pass writes its output with the new mode first).
+@pytest.mark.parametrize("shape,diag,nrhs", [((256, 256, 256), True, 2), ((512, 256, 256), False, 1)])
+def test_matvec_fp32_dense_gemm3_path(shape, diag, nrhs):
+    import torch
+    from gpu_util import make_op, pack, unpack
+    s = _systems(shape, 1, diag, seed=7)
+    X = np.random.default_rng(8).standard_normal((nrhs, s.n))
+    op = make_op([s], prec="fp32")
+    Y = unpack(op.matvec(pack([X], torch.float32), nrhs), [s], nrhs)[0]
+    Xr = lowprec.to_fp32(X)
+    ref = kron.mvm(s.factors, Xr, s.sigma2, s.diag)
+    absref = kron.mvm([[np.abs(f) for f in row] for row in s.factors], np.abs(Xr), abs(s.sigma2),
+                      None if s.diag is None else np.abs(s.diag))
+    # three FP32-accumulated contractions of length 256 and 512
+    err = (np.abs(Y - ref) / absref).max()
+    assert err <= 1e-5, err
+    op.close()

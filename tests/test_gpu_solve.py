@@ -82,6 +82,20 @@ def test_refined_bf16_dense_gemm_path():
         assert abs(i["relres"] - r) <= 1e-3 * r + 1e-15
 
 
+def test_refined_fp32_dense_gemm3_path():
+    """256^3 Wishart-factor operator (condition number ~1e2, a few hundred iterations): FP32 CG on the
+    three-GEMM MVM with FP64 reliable updates reaches 1e-6 true residual, certified by the oracle."""
+    rng = np.random.default_rng(93)
+    s = wl.random_system(rng, (256, 256, 256), nterms=1, diag=False, sigma2=0.5)
+    B = rng.standard_normal((2, s.n))
+    (X,), info = _solve([s], [B], "fp32", 2, tol=1e-6, max_iters=3000, inner_tol=0.1)
+    assert all(i["status"] == 0 for i in info), info
+    rr = kron.relres(s.factors, X, B, s.sigma2)
+    assert np.all(rr <= 1e-6), rr
+    for i, r in zip(info, rr):
+        assert abs(i["relres"] - r) <= 1e-3 * r + 1e-15
+
+
 def test_refined_uneven_batch_fp32():
     w = wl.config3(nsys=6, dmin=5, dmax=40)
     (Xs), info = _solve(w.systems, w.B, "fp32", 1, tol=1e-8, max_iters=3000)
