@@ -262,7 +262,11 @@ __global__ __launch_bounds__(kThreads) void k_gemm2_y(Gemm2Args a) {
     const float s2 = (float)a.sigma2;
     constexpr int FP = 32 + 4;                             // staging pitch (floats)
     float* Ef = (float*)smem + wave * 128 * FP;            // [128 rows][32 columns]
-    double dot = 0.0;
+    // chunk c of slice jj: row c*8 + lane/8, columns (lane % 8)*4 .. +3 of the slice;
+    // the lane part of the offset is fixed, the rest uniform
+    const int64_t lane_e = (int64_t)(a0 + wm * 128 + (lane >> 3)) * a.n2 + b0 + wn * 128 + (lane & 7) * 4;
+    auto e_of = [&](int jj, int c) -> int64_t { return lane_e + (int64_t)(8 * c) * a.n2 + jj * 32; };
+    double dacc[4] = {0.0, 0.0, 0.0, 0.0};                 // p.q in FP64, four short chains
 #pragma unroll
     for (int jj = 0; jj < 4; ++jj) {
 #pragma unroll
@@ -274,7 +278,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm2_y(Gemm2Args a) {
         for (int c = 0; c < 16; ++c) {
             const int id = lane + 64 * c;
             const int row = id >> 3, c4 = (id & 7) * 4;
-            const int64_t e = (int64_t)(a0 + wm * 128 + row) * a.n2 + b0 + wn * 128 + jj * 32 + c4;
+            const int64_t e = e_of(jj, c);
             const floatx4 y = *(const floatx4*)&Ef[row * FP + c4];
             const floatx4 p = *(const floatx4*)(Pr + e);
             floatx4 dg = floatx4{s2, s2, s2, s2};
@@ -283,12 +287,13 @@ __global__ __launch_bounds__(kThreads) void k_gemm2_y(Gemm2Args a) {
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 q[u] = y[u] + dg[u] * p[u];
-                dot += (double)p[u] * (double)q[u];
+                dacc[u] = __builtin_fma((double)p[u], (double)q[u], dacc[u]);
             }
             *(floatx4*)(Yr + e) = q;
         }
         __syncthreads();
     }
+    const double dot = (dacc[0] + dacc[1]) + (dacc[2] + dacc[3]);
     if (!cg) return;
     const double s = block_sum(dot, red);
     double tot;

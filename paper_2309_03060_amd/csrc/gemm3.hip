@@ -151,31 +151,43 @@ __global__ __launch_bounds__(kThreads) void k_gemm3(Gemm3Args a, PassDesc d) {
     const int64_t rhs_base = (int64_t)r * d.N * d.rows_per_rhs;
     float* Ef = smem + wave * 32 * TP;
     const float s2 = (float)a.sigma2;
-    double dot = 0.0;
+    double dacc[4] = {0.0, 0.0, 0.0, 0.0};                 // p.q in FP64, four short chains
+    // chunk c of slice jt: column jt*32 + 2c + lane/32, rows (lane % 32)*4 .. +3 of the
+    // wave's sub-tile; the lane part of the offset is fixed, the rest uniform
+    const int64_t lane_pos = (int64_t)(n0 + wn * 128 + (lane >> 5)) * d.rows_per_rhs + mloc + (lane & 31) * 4;
+    auto pos_of = [&](int jt, int c) -> int64_t { return lane_pos + (int64_t)(jt * 32 + 2 * c) * d.rows_per_rhs; };
+    // the direction (or x) of a slice is loaded before the slice is staged, so
+    // its latency overlaps the staging and the barrier
+    floatx4 pv[EPI == EPI_STORE ? 1 : 16];
 #pragma unroll
     for (int jt = 0; jt < 4; ++jt) {
+        __builtin_amdgcn_sched_barrier(0);                 // one slice's loads in flight at a time
+        if constexpr (EPI != EPI_STORE) {
+#pragma unroll
+            for (int c = 0; c < 16; ++c) pv[c] = *(const floatx4*)(a.X + rhs_base + pos_of(jt, c));
+        }
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
             for (int v = 0; v < 16; ++v) Ef[(lane & 31) * TP + i * 32 + row32(lane, v)] = acc[i][jt][v];
         __syncthreads();
-#pragma unroll 4
+#pragma unroll
         for (int c = 0; c < 16; ++c) {
             const int id = lane + 64 * c;
             const int col = id >> 5, m4 = (id & 31) * 4;
-            const int64_t pos = (int64_t)(n0 + wn * 128 + jt * 32 + col) * d.rows_per_rhs + mloc + m4;
+            const int64_t pos = pos_of(jt, c);
             const floatx4 y = *(const floatx4*)&Ef[col * TP + m4];
             if constexpr (EPI == EPI_STORE) {
                 *(floatx4*)(d.Out + rhs_base + pos) = y;
             } else {
-                const floatx4 p = *(const floatx4*)(a.X + rhs_base + pos);   // p_new (CG) or x
+                const floatx4 p = pv[c];                                       // p_new (CG) or x
                 floatx4 dg = floatx4{s2, s2, s2, s2};
                 if (a.dvec) dg += *(const floatx4*)(a.dvec + pos);
                 floatx4 q;
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     q[u] = y[u] + dg[u] * p[u];
-                    if constexpr (EPI == EPI_CG) dot += (double)p[u] * (double)q[u];
+                    if constexpr (EPI == EPI_CG) dacc[u] = __builtin_fma((double)p[u], (double)q[u], dacc[u]);
                 }
                 *(floatx4*)(d.Out + rhs_base + pos) = q;
             }
@@ -183,7 +195,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm3(Gemm3Args a, PassDesc d) {
         __syncthreads();
     }
     if constexpr (EPI == EPI_CG) {
-        const double sum = block_sum(dot, red);
+        const double sum = block_sum((dacc[0] + dacc[1]) + (dacc[2] + dacc[3]), red);
         const int tpr = (int)(d.rows_per_rhs / BM) * Nt;
         const int t = (int)((m0 - (int64_t)r * d.rows_per_rhs) / BM) * Nt + nt;
         double tot;
