@@ -18,6 +18,7 @@
 #include "gemm.h"
 
 #include <algorithm>
+#include <type_traits>
 
 #include "contract.h"
 
@@ -92,9 +93,14 @@ __device__ inline void gemm_tile(floatx16 (&acc)[4][4], int nk, ABase abase, int
 #pragma unroll
             for (int j = 0; j < 4; ++j) acc[i][j] = mfma32(av[i], bv[j], acc[i][j]);
     };
-    // one k slice from LDS stage `buf`: the fragments of step kk + 16 are read
-    // while the MFMAs of step kk run
-    auto compute = [&](int buf) {
+    // One k slice from LDS stage `buf` while the next slice (registers ra, rb)
+    // is written to stage `sbuf`: the fragments of step kk + 16 are read while
+    // the MFMAs of step kk run, and the sixteen LDS writes are spread one per
+    // four MFMAs (scheduling groups), so the matrix cores never wait for a
+    // burst of writes.  Both stage indices are compile-time constants, which
+    // lets the compiler see that the writes and the reads do not overlap.
+    auto compute_stage = [&](auto buf_c, const u32x4 (&ra)[kChunks], const u32x4 (&rb)[kChunks], auto sbuf_c) {
+        constexpr int buf = decltype(buf_c)::value, sbuf = decltype(sbuf_c)::value;
         const __bf16* As = smem + buf * kStage;
         const __bf16* Bs = As + BM * KSP;
         bf16x8 a0[4], b0[4], a1[4], b1[4];
@@ -106,10 +112,24 @@ __device__ inline void gemm_tile(floatx16 (&acc)[4][4], int nk, ABase abase, int
         frags(a1, b1, As, Bs, 48);
         mma16(a0, b0);
         mma16(a1, b1);
+        stage(ra, rb, sbuf);
+        __builtin_amdgcn_sched_group_barrier(0x100, 16, 0);        // fragments of steps 0 and 16
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                __builtin_amdgcn_sched_group_barrier(0x008, 4, 0);  // 4 MFMAs
+                __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);  // 1 LDS write of the next slice
+            }
+            if (g < 2) __builtin_amdgcn_sched_group_barrier(0x100, 8, 0);   // fragments of step 32 / 48
+        }
     };
     // Two LDS stages and two register sets: while slice s is multiplied from
     // LDS, slice s + 1 (already in registers) is written to the other stage and
-    // slice s + 2 is in flight from memory.  nk is a multiple of 2 KS.
+    // slice s + 2 is in flight from memory.  nk is a multiple of 2 KS.  The
+    // last half-iteration stages a (clamped, valid) slice nobody reads.
+    using C0 = std::integral_constant<int, 0>;
+    using C1 = std::integral_constant<int, 1>;
     u32x4 ra0[kChunks], rb0[kChunks], ra1[kChunks], rb1[kChunks];
     load(ra0, rb0, 0);
     load(ra1, rb1, KS);
@@ -118,13 +138,11 @@ __device__ inline void gemm_tile(floatx16 (&acc)[4][4], int nk, ABase abase, int
     for (int k0 = 0; k0 < nk; k0 += 2 * KS) {
         load(ra0, rb0, k0 + 2 * KS);
         __builtin_amdgcn_sched_barrier(0);                 // keep the loads ahead of the MFMAs
-        compute(0);
-        stage(ra1, rb1, 1);
+        compute_stage(C0{}, ra1, rb1, C1{});
         __syncthreads();
         load(ra1, rb1, k0 + 3 * KS);
         __builtin_amdgcn_sched_barrier(0);
-        compute(1);
-        if (k0 + 2 * KS < nk) stage(ra0, rb0, 0);
+        compute_stage(C1{}, ra0, rb0, C0{});
         __syncthreads();
     }
 }
