@@ -366,22 +366,27 @@ struct ReliableTail {
     float* rl;        // low-precision residual
 };
 
-int32_t enqueue_tail(cola_op_s* op, const SysInfo& s, int nrhs, const ReliableTail& t, bool all_rhs,
+// final == false: the reliable update of the right-hand sides that asked for
+// one (fold, FP64 residual, replace r and resume or finish).  final == true:
+// after the last chunk, fold and form the FP64 residual only for the
+// right-hand sides whose last true residual is stale (status not OK: iteration
+// limit, breakdown); a converged one was certified by its last update and its
+// x has not changed since.
+int32_t enqueue_tail(cola_op_s* op, const SysInfo& s, int nrhs, const ReliableTail& t, bool final,
                      hipStream_t st) {
     Workspace& w = op->ws;
-    HIP_TRY(reliable_fold<float>(t.X, t.xl, s.n, nrhs, w.cg, all_rhs, st));
+    if (final) HIP_TRY(mark_unverified(w.cg, nrhs, st));
+    HIP_TRY(reliable_fold<float>(t.X, t.xl, s.n, nrhs, w.cg, false, st));
     PassArgs a = base_args(op);
     a.cg = w.cg;
-    if (!all_rhs) {
-        a.gate = &w.cg->need_update;
-        a.gate_stride = (int32_t)(sizeof(CgState) / sizeof(int32_t));
-    }
+    a.gate = &w.cg->need_update;
+    a.gate_stride = (int32_t)(sizeof(CgState) / sizeof(int32_t));
     a.epi = EPI_RESID_CG;
     a.Ep = t.X;
     a.Er = t.B;
     int32_t rc = enqueue_mvm(op, s, COLA_PREC_FP64, nrhs, t.X, nullptr, w.r64, a, st);
     if (rc != COLA_OK) return rc;
-    if (!all_rhs)
+    if (!final)
         HIP_TRY(reliable_apply<float>(w.r64, t.rl, s.n, nrhs, w.cg, w.partials, (int)w.part_stride, w.counters,
                                       w.cnt, st));
     return COLA_OK;
@@ -562,7 +567,7 @@ int32_t solve_system(cola_op_s* op, const SysInfo& s, const double* B, double* X
         ReliableTail tail{w.x64, w.b64, xl, rl};
         int32_t rc = run_cg<float>(op, s, op->prec, nrhs, xl, rl, pl, ql, o->max_iters, o->check_every, &tail, st);
         if (rc != COLA_OK) return rc;
-        rc = enqueue_tail(op, s, nrhs, tail, true, st);       // final fold and true residual for every RHS
+        rc = enqueue_tail(op, s, nrhs, tail, true, st);       // final fold and true residual where stale
         if (rc != COLA_OK) return rc;
         HIP_TRY(copy_f64(w.x64, X, (int64_t)nrhs * n, st));
         if (info) HIP_TRY(write_info(info, nullptr, w.cg, nrhs, st));

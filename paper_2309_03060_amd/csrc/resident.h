@@ -30,7 +30,7 @@ struct ResArgs {
     double* t64;                    // packed FP64 scratch (residual intermediate)
     CgState* st;                    // per item
     SolveCounters* cnt;
-    int32_t all_items;              // residual kernel: every item (final pass) instead of requested ones
+    int32_t all_items;              // residual kernel: final pass (items without a certified residual)
 };
 
 constexpr int kResMax = 128;        // largest mode size handled by the resident kernel

@@ -270,15 +270,17 @@ __global__ __launch_bounds__(kResThreads) void k_resident_cg(ResArgs a) {
     }
 }
 
-// FP64 residual of requested items (all items when a.all_items): fold the
-// FP32 iterate into the FP64 solution, r = b - (K1 X K2^T + (sigma2 + d) x)
-// with the FP64 factors, r_lo = r; then the reliable-update decision.
+// FP64 residual of requested items: fold the FP32 iterate into the FP64
+// solution, r = b - (K1 X K2^T + (sigma2 + d) x) with the FP64 factors,
+// r_lo = r; then the reliable-update decision.  Final pass (a.all_items):
+// every item without a certified residual (status not OK); a converged item
+// was certified by its last update and its x has not changed since.
 __global__ __launch_bounds__(kThreads) void k_resident_resid64(ResArgs a) {
     __shared__ double Xs[kResMax * kResMax];
     __shared__ double red[4];
     const int item = blockIdx.x;
     CgState& st = a.st[item];
-    if (!a.all_items && !st.need_update) return;
+    if (a.all_items ? st.status == COLA_OK : !st.need_update) return;
     const ResSys sy = a.sys[item / a.nrhs];
     const int rhs = item % a.nrhs;
     const int n1 = sy.n1, n2 = sy.n2;

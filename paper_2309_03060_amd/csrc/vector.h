@@ -37,6 +37,7 @@ hipError_t refine_accumulate(double* x64, const T* d, int64_t n, int nrhs, const
 
 hipError_t outer_bookkeep(OuterState* outer, const CgState* cg, int nrhs, SolveCounters* cnt, hipStream_t s);
 hipError_t write_info(cola_solve_info* info, const OuterState* outer, const CgState* cg, int nrhs, hipStream_t s);
+hipError_t mark_unverified(CgState* cg, int nrhs, hipStream_t s);
 
 hipError_t convert_f64_f32(const double* in, float* out, int64_t n, hipStream_t s);
 hipError_t convert_f32_f64(const float* in, double* out, int64_t n, hipStream_t s);

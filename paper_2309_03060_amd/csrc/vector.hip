@@ -304,6 +304,13 @@ __global__ void k_write_info(cola_solve_info* info, const OuterState* outer, con
     info[g] = o;
 }
 
+// need_update = 1 exactly for the right-hand sides that did not finish with a
+// certified true residual (used by the final fold of a reliable-update solve).
+__global__ void k_mark_unverified(CgState* cg, int nrhs) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < nrhs) cg[g].need_update = cg[g].status != COLA_OK ? 1 : 0;
+}
+
 // ---------------------------------------------------------------------------
 // Factor / vector conversions (round to nearest even at every narrowing).
 __global__ void k_f64_to_f32(const double* in, float* out, int64_t n) {
@@ -430,6 +437,11 @@ hipError_t outer_bookkeep(OuterState* outer, const CgState* cg, int nrhs, SolveC
 
 hipError_t write_info(cola_solve_info* info, const OuterState* outer, const CgState* cg, int nrhs, hipStream_t s) {
     hipLaunchKernelGGL(k_write_info, dim3((nrhs + 255) / 256), dim3(256), 0, s, info, outer, cg, nrhs);
+    return hipGetLastError();
+}
+
+hipError_t mark_unverified(CgState* cg, int nrhs, hipStream_t s) {
+    hipLaunchKernelGGL(k_mark_unverified, dim3((nrhs + 255) / 256), dim3(256), 0, s, cg, nrhs);
     return hipGetLastError();
 }
 
