@@ -172,6 +172,20 @@ int32_t cola_cg_solve_backward(cola_op_t op, const double* X, const double* G, i
                                void* const* dfactors, void* const* ddiag, double* dsigma2,
                                cola_solve_info* info, void* stream);
 
+/* Direct solve X = A^{-1} B of single-term systems A = K_1 (x) .. (x) K_F +
+ * sigma2 * I by the Kronecker eigenvalue rules (App. A: the eigenvectors of a
+ * Kronecker product are the Kronecker products of the factors' eigenvectors
+ * and its eigenvalues the products of theirs; Sec. 3 dispatches solves of
+ * such structure this way instead of iterating):
+ *     X = (Q_1 (x) .. (x) Q_F) [ ((Q_1 (x) .. (x) Q_F)^T B) ./ (lam_1 (x) .. (x) lam_F + sigma2) ].
+ * The factors must be symmetric positive semi-definite.  The first call
+ * decomposes every factor on the device (FP64 one-sided Jacobi; it waits on
+ * the stream once per sweep) and keeps the eigenvectors; later calls are two
+ * FP64 Kronecker MVMs and one scaling, enqueued on `stream`.  B and X are
+ * packed FP64 vectors as for cola_cg_solve and must not overlap.  Returns
+ * COLA_ERR_UNSUPPORTED if any system has more than one term or a diagonal. */
+int32_t cola_eig_solve(cola_op_t op, const double* B, double* X, int32_t nrhs, void* stream);
+
 /* Pick kernel tile shapes for this op and nrhs by timing the candidates on
  * `stream` (synchronises it).  Optional: without it a fixed default is used. */
 int32_t cola_autotune(cola_op_t op, int32_t nrhs, void* stream);

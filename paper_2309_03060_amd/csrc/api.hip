@@ -11,6 +11,7 @@
 #include <new>
 
 #include "gemm.h"
+#include "eig.h"
 #include "gemm3.h"
 #include "grad.h"
 #include "op.h"
@@ -886,6 +887,106 @@ int32_t cola_op_create(const cola_system_desc* systems, int32_t nsys, int32_t pr
     return COLA_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Kronecker-eigen solve: decompose every factor once (FP64 one-sided Jacobi),
+// keep the eigenvector factors as two internal operators (Q^T and Q) and the
+// eigenvalues; a solve is then two Kronecker MVMs and one scaling.
+namespace {
+int32_t ensure_eig(cola_op_s* op, hipStream_t st) {
+    if (op->eig_q) return COLA_OK;
+    for (const SysInfo& s : op->sys)
+        if (s.J != 1 || s.diag_off >= 0) return COLA_ERR_UNSUPPORTED;
+    int64_t nmax = 1, lam_total = 0, vec_total = 0;
+    op->eig_lam_off.assign(op->sys.size(), {0, 0, 0});
+    for (size_t i = 0; i < op->sys.size(); ++i) {
+        const SysInfo& s = op->sys[i];
+        for (int k = 0; k < s.Fv; ++k) {
+            nmax = std::max(nmax, s.dims[k]);
+            op->eig_lam_off[i][k] = lam_total;
+            lam_total += s.dims[k];
+            vec_total += s.dims[k] * s.dims[k];
+        }
+    }
+    double *vt = nullptr, *q = nullptr, *work = nullptr, *off = nullptr;
+    int32_t rc = alloc_bytes((void**)&op->eig_lam, sizeof(double) * lam_total);
+    rc |= alloc_bytes((void**)&vt, sizeof(double) * vec_total);
+    rc |= alloc_bytes((void**)&q, sizeof(double) * vec_total);
+    rc |= alloc_bytes((void**)&work, sizeof(double) * nmax * nmax);
+    rc |= alloc_bytes((void**)&off, sizeof(double) * 2);
+    auto cleanup = [&]() {
+        for (void* p : {(void*)vt, (void*)q, (void*)work, (void*)off})
+            if (p) (void)hipFree(p);
+    };
+    if (rc != COLA_OK) {
+        (void)hipStreamSynchronize(st);
+        cleanup();
+        return COLA_ERR_OOM;
+    }
+    std::vector<std::array<const void*, 3>> fqt(op->sys.size()), fq(op->sys.size());
+    std::vector<cola_system_desc> dqt(op->sys.size()), dq(op->sys.size());
+    int64_t voff = 0;
+    for (size_t i = 0; i < op->sys.size() && rc == COLA_OK; ++i) {
+        const SysInfo& s = op->sys[i];
+        for (int k = 0; k < s.Fv && rc == COLA_OK; ++k) {
+            const int64_t nk = s.dims[k];
+            rc = jacobi_eig(op->fac64 + s.fac_off[k], nk, vt + voff, op->eig_lam + op->eig_lam_off[i][k], work,
+                            off, 4e-15, 40, st);
+            if (rc == COLA_OK && transpose_f64(vt + voff, q + voff, nk, st) != hipSuccess) rc = COLA_ERR_HIP;
+            fqt[i][k] = vt + voff;             // column-major V is the row-major Q^T
+            fq[i][k] = q + voff;
+            voff += nk * nk;
+        }
+        for (auto* d : {&dqt[i], &dq[i]}) {
+            std::memset(d, 0, sizeof(*d));
+            d->nterms = 1;
+            d->nfactors = s.Fv;
+            for (int k = 0; k < s.Fv; ++k) d->dims[k] = s.dims[k];
+            d->sigma2 = 0.0;
+        }
+        dqt[i].factors = fqt[i].data();
+        dq[i].factors = fq[i].data();
+    }
+    if (rc == COLA_OK) rc = cola_op_create(dqt.data(), (int32_t)dqt.size(), COLA_PREC_FP64, st, &op->eig_qt);
+    if (rc == COLA_OK) rc = cola_op_create(dq.data(), (int32_t)dq.size(), COLA_PREC_FP64, st, &op->eig_q);
+    (void)hipStreamSynchronize(st);                        // the operators own copies now
+    cleanup();
+    if (rc != COLA_OK) {
+        if (op->eig_qt) cola_op_destroy(op->eig_qt);
+        if (op->eig_q) cola_op_destroy(op->eig_q);
+        op->eig_qt = op->eig_q = nullptr;
+        (void)hipFree(op->eig_lam);
+        op->eig_lam = nullptr;
+    }
+    return rc;
+}
+}  // namespace
+
+int32_t cola_eig_solve(cola_op_t op, const double* B, double* X, int32_t nrhs, void* stream) {
+    if (!op || !B || !X || nrhs < 1) return COLA_ERR_INVALID_ARG;
+    hipStream_t st = S(stream);
+    int32_t rc = ensure_eig(op, st);
+    if (rc != COLA_OK) return rc;
+    const int64_t need = (int64_t)nrhs * op->n_total;
+    if (op->eig_tmp_elems < need) {
+        (void)hipStreamSynchronize(st);
+        if (op->eig_tmp) (void)hipFree(op->eig_tmp);
+        op->eig_tmp = nullptr;
+        op->eig_tmp_elems = 0;
+        if (alloc_bytes((void**)&op->eig_tmp, sizeof(double) * need) != COLA_OK) return COLA_ERR_OOM;
+        op->eig_tmp_elems = need;
+    }
+    rc = cola_kron_matvec(op->eig_qt, B, op->eig_tmp, nrhs, COLA_F64, COLA_PREC_FP64, stream);
+    if (rc != COLA_OK) return rc;
+    for (size_t i = 0; i < op->sys.size(); ++i) {
+        const SysInfo& s = op->sys[i];
+        const double* lam[3] = {nullptr, nullptr, nullptr};
+        for (int k = 0; k < s.Fv; ++k) lam[k] = op->eig_lam + op->eig_lam_off[i][k];
+        double* y = op->eig_tmp + (int64_t)nrhs * s.vec_off;
+        HIP_TRY(eig_scale(y, y, nrhs, s.Fv, s.dims, lam, s.sigma2, st));
+    }
+    return cola_kron_matvec(op->eig_q, op->eig_tmp, X, nrhs, COLA_F64, COLA_PREC_FP64, stream);
+}
+
 int32_t cola_op_destroy(cola_op_t op) {
     if (!op) return COLA_OK;
     (void)hipDeviceSynchronize();
@@ -893,7 +994,10 @@ int32_t cola_op_destroy(cola_op_t op) {
     if (op->cap_stream) (void)hipStreamDestroy(op->cap_stream);
     free_resident(op);
     free_ws(op->ws);
-    void* ptrs[] = {op->fac64, op->fac32, op->facbf, op->diag64, op->diag32, op->grad_buf};
+    if (op->eig_qt) cola_op_destroy(op->eig_qt);
+    if (op->eig_q) cola_op_destroy(op->eig_q);
+    void* ptrs[] = {op->fac64, op->fac32, op->facbf, op->diag64, op->diag32, op->grad_buf, op->eig_lam,
+                    op->eig_tmp};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     delete op;

@@ -1,5 +1,6 @@
 // Operator handle and workspace (host side of libcola).
 #pragma once
+#include <array>
 #include <map>
 #include <tuple>
 #include <string>
@@ -134,6 +135,14 @@ struct cola_op_s {
     uint32_t* res_queue = nullptr;
     hipStream_t cap_stream = nullptr;
     std::map<cola::GraphKey, cola::GraphSet> graphs;
+    // Kronecker-eigen solve: operators of the eigenvector factors Q^T and Q
+    // (one term per system, FP64), eigenvalues per system and mode, scratch
+    cola_op_s* eig_qt = nullptr;
+    cola_op_s* eig_q = nullptr;
+    double* eig_lam = nullptr;
+    std::vector<std::array<int64_t, 3>> eig_lam_off;
+    double* eig_tmp = nullptr;
+    int64_t eig_tmp_elems = 0;
 };
 
 namespace cola {

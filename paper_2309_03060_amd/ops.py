@@ -184,6 +184,16 @@ class KronOperator:
             ctypes.cast(da, ctypes.POINTER(ctypes.c_void_p)), ds2.data_ptr(), info.data_ptr(), _stream_ptr()))
         return Lam, (dfac if want_factors else None), ddiag, ds2, info
 
+    def eig_solve(self, B: torch.Tensor, nrhs: int) -> torch.Tensor:
+        """X = A^{-1} B for single-term Kronecker + sigma2 I systems by the Kronecker eigen rules
+        (cola_eig_solve); the factors' eigendecomposition is computed on the first call."""
+        if B.dtype != torch.float64 or not B.is_contiguous():
+            raise ValueError("B must be a contiguous float64 device tensor")
+        X = torch.empty_like(B)
+        L.check("cola_eig_solve", self.lib.cola_eig_solve(self.handle, B.data_ptr(), X.data_ptr(), nrhs,
+                                                           _stream_ptr()))
+        return X
+
     def autotune(self, nrhs: int):
         L.check("cola_autotune", self.lib.cola_autotune(self.handle, nrhs, _stream_ptr()))
 
