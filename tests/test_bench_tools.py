@@ -1,0 +1,71 @@
+"""CPU checks of the benchmark's host-side tooling: launch-class names of kernels, the rocprofv3 counter
+summary (reference-copy scaling, set-up dispatches dropped) and the source-keyed traffic record."""
+import csv
+import json
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+@pytest.mark.parametrize("name,cls", [
+    ("void cola::k_contract<cola::PolF32, 1, 4, false>(cola::PassArgs)", "contract_cols_f32"),
+    ("void cola::k_contract<cola::PolBF16, 2, 2, true>(cola::PassArgs)", "contract_rows_bf16"),
+    ("void cola::k_slab23<cola::SlabF64, true, false>(cola::SlabArgs)", "slab23_f64"),
+    ("void cola::k_cg_update<float>(float*, float*, float const*, float const*, long)", "update_float"),
+    ("cola::(anonymous namespace)::k_gemm2_t(cola::Gemm2Args)", "k_gemm2_t"),
+    ("__amd_rocclr_copyBuffer", "other"),
+])
+def test_kernel_class(name, cls):
+    assert bench.kernel_class(name) == cls
+
+
+def _write_csv(path, rows):
+    keys = ["Dispatch_Id", "Kernel_Name", "Grid_Size", "Counter_Name", "Counter_Value", "Start_Timestamp",
+            "End_Timestamp"]
+    with open(path, "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=keys)
+        w.writeheader()
+        for r in rows:
+            w.writerow(dict(zip(keys, r)))
+
+
+def test_pmc_summary_scales_by_reference_copy(tmp_path, capsys):
+    mul = "void at::native::vectorized_elementwise_kernel<4, at::native::AUnaryFunctor<float, float, float, " \
+          "at::native::binary_internal::MulFunctor<float> > >"
+    upd = "void cola::k_cg_update<float>(float*)"
+    fetch, write = tmp_path / "f.csv", tmp_path / "w.csv"
+    # set-up dispatch (dropped), elementwise reference, runtime copy (marker), two solver dispatches
+    _write_csv(fetch, [(1, upd, 64, "FETCH_SIZE", 999.0, 0, 1000), (2, mul, 64, "FETCH_SIZE", 131072.0, 0, 1000),
+                       (3, "__amd_rocclr_copyBuffer", 64, "FETCH_SIZE", 131072.0, 0, 1000),
+                       (4, upd, 64, "FETCH_SIZE", 100.0, 0, 2000), (5, upd, 64, "FETCH_SIZE", 300.0, 0, 4000)])
+    _write_csv(write, [(1, upd, 64, "WRITE_SIZE", 999.0, 0, 1000), (2, mul, 64, "WRITE_SIZE", 262144.0, 0, 1000),
+                       (3, "__amd_rocclr_copyBuffer", 64, "WRITE_SIZE", 262144.0, 0, 1000),
+                       (4, upd, 64, "WRITE_SIZE", 50.0, 0, 2000), (5, upd, 64, "WRITE_SIZE", 150.0, 0, 4000)])
+    out = tmp_path / "traffic.json"
+    bench.pmc_summary([str(fetch), str(write)], "c2", str(out))
+    rec = json.load(open(out))["c2"]
+    assert rec["scale"]["FETCH_SIZE"] == pytest.approx(2.0)
+    assert rec["scale"]["WRITE_SIZE"] == pytest.approx(1.0)
+    upd_rec = rec["kernels"]["update"]
+    # averages over the two solver dispatches only: fetch 200 KiB x 2, write 100 KiB x 1
+    assert upd_rec["bytes_per_launch_all_rhs_active"] == 1024 * (200 * 2 + 100)
+    assert upd_rec["sources_sha1"] == bench.sources_digest("update")
+    assert "update_float | 2 |" in capsys.readouterr().out
+
+
+def test_measured_traffic_follows_active_rhs_and_sources(tmp_path, monkeypatch):
+    rec = {"c2": {"scale": {}, "kernels": {"update": {"bytes_per_launch_all_rhs_active": 3200,
+                                                      "sources_sha1": bench.sources_digest("update")}}}}
+    path = tmp_path / "t.json"
+    path.write_text(json.dumps(rec))
+    monkeypatch.setattr(bench, "PMC_FILE", str(path))
+    # 10 launches carrying 160 RHS*iterations of 32 RHS: half active on average
+    assert bench.measured_traffic("c2", "update", 32, 160, 10) == 1600
+    rec["c2"]["kernels"]["update"]["sources_sha1"] = "stale"
+    path.write_text(json.dumps(rec))
+    assert bench.measured_traffic("c2", "update", 32, 160, 10) is None
