@@ -11,14 +11,14 @@
 //
 // G1 stores T transposed per right-hand side (T_r[b][(j, a')]) so that both
 // GEMMs take their operands k-contiguous.  Block tile 256 x 256, k slice 64,
-// 4 waves each owning 128 x 128 (4 x 4 MFMA tiles); two LDS stages and two
-// register sets keep two k slices in flight while one is multiplied.
+// 8 waves (two per SIMD, so one wave's LDS and memory waits overlap the
+// other's MFMAs) each owning 128 x 64 (4 x 2 MFMA tiles); two LDS stages, the
+// next k slice loaded into registers while the current one is multiplied.
 // Block indices are mapped so that each XCD works on a contiguous group of
 // tiles that share operand panels in its L2.
 #include "gemm.h"
 
 #include <algorithm>
-#include <type_traits>
 
 #include "contract.h"
 
@@ -30,9 +30,46 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 namespace {
 
 constexpr int BM = 256, BN = 256, KS = 64;
+constexpr int kGT = 512;                         // threads of the GEMM kernels (8 waves)
 constexpr int KSP = KS + 8;                      // LDS row pitch (bf16): conflict-free 16-byte reads
-constexpr int kChunks = BM * KS / 8 / kThreads;  // 16-byte chunks of one operand slice per thread
+constexpr int kChunks = BM * KS / 8 / kGT;       // 16-byte chunks of one operand slice per thread
 constexpr int kStage = (BM + BN) * KSP;          // bf16 elements of one LDS stage (A and B slices)
+
+// Block sum over the 8 waves of a GEMM block (fixed order); valid in every thread.
+__device__ inline double block_sum8(double v, double* smem8) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) smem8[wave] = v;
+    __syncthreads();
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < 8; ++w) t += smem8[w];
+    __syncthreads();
+    return t;
+}
+
+// The last-block-done reduction of common.h for 8-wave blocks.
+__device__ inline bool last_block_reduce8(double partial, double* partials, uint32_t* counter, int nblocks,
+                                          int myblock, double* total, double* smem8) {
+    __shared__ int s_last;
+    if (threadIdx.x == 0) {
+        store_coherent(&partials[myblock], partial);
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        __builtin_amdgcn_s_waitcnt(0);            // the partial store has completed
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        const uint32_t prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_last = (prev == (uint32_t)(nblocks - 1));
+    }
+    __syncthreads();
+    if (!s_last) return false;
+    double t = 0.0;
+    for (int i = threadIdx.x; i < nblocks; i += blockDim.x) t += load_coherent(&partials[i]);
+    t = block_sum8(t, smem8);
+    if (threadIdx.x == 0) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    *total = t;
+    return true;
+}
 
 __device__ inline floatx16 mfma32(bf16x8 a, bf16x8 b, floatx16 c) {
     return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
@@ -47,103 +84,65 @@ __device__ inline int xcd_linear(int b, int T) {
     return (T % 8 == 0) ? (b % 8) * (T / 8) + b / 8 : b;
 }
 
-// acc += A_tile * B_tile^T over k in [0, nk).  abase(k0) / bbase(k0) give the
-// (block-uniform) address of row 0, column k0 of the A / B tile; rows are lda /
-// ldb elements apart and every row segment is 16-byte aligned.  Each thread
-// loads rows crow + 32 q at one per-thread offset from a uniform base, which
-// keeps the address arithmetic in scalar registers.
+// acc += A_tile * B_tile^T over k in [0, nk) for this wave's 128 x 64 part.
+// abase(k0) / bbase(k0) give the (block-uniform) address of row 0, column k0
+// of the A / B tile; rows are lda / ldb elements apart and every row segment
+// is 16-byte aligned.  Each thread loads rows crow + 64 q at one per-thread
+// offset from a uniform base, keeping the address arithmetic scalar.
 template <class ABase, class BBase>
-__device__ inline void gemm_tile(floatx16 (&acc)[4][4], int nk, ABase abase, int64_t lda, BBase bbase, int64_t ldb,
+__device__ inline void gemm_tile(floatx16 (&acc)[4][2], int nk, ABase abase, int64_t lda, BBase bbase, int64_t ldb,
                                  __bf16* smem) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave >> 1, wn = wave & 1;
+    const int wm = wave >> 2, wn = wave & 3;
     const int crow = tid >> 3, ck = (tid & 7) * 8;
     const uint32_t aoff = (uint32_t)(crow * lda + ck), boff = (uint32_t)(crow * ldb + ck);
     const int klast = nk - KS;
-    auto load = [&](u32x4 (&ra)[kChunks], u32x4 (&rb)[kChunks], int k0) {
+    u32x4 ra[kChunks], rb[kChunks];
+    auto load = [&](int k0) {
         k0 = k0 < klast ? k0 : klast;                      // clamped, so the loads are unconditional
         const __bf16* a0 = abase(k0);
         const __bf16* b0 = bbase(k0);
 #pragma unroll
         for (int q = 0; q < kChunks; ++q) {
-            ra[q] = *(const u32x4*)(a0 + (int64_t)q * 32 * lda + aoff);
-            rb[q] = *(const u32x4*)(b0 + (int64_t)q * 32 * ldb + boff);
+            ra[q] = *(const u32x4*)(a0 + (int64_t)q * 64 * lda + aoff);
+            rb[q] = *(const u32x4*)(b0 + (int64_t)q * 64 * ldb + boff);
         }
     };
-    auto stage = [&](const u32x4 (&ra)[kChunks], const u32x4 (&rb)[kChunks], int buf) {
+    auto stage = [&](int buf) {
         __bf16* As = smem + buf * kStage;
         __bf16* Bs = As + BM * KSP;
 #pragma unroll
         for (int q = 0; q < kChunks; ++q) {
-            *(u32x4*)&As[(crow + 32 * q) * KSP + ck] = ra[q];
-            *(u32x4*)&Bs[(crow + 32 * q) * KSP + ck] = rb[q];
+            *(u32x4*)&As[(crow + 64 * q) * KSP + ck] = ra[q];
+            *(u32x4*)&Bs[(crow + 64 * q) * KSP + ck] = rb[q];
         }
     };
-    auto frags = [&](bf16x8 (&av)[4], bf16x8 (&bv)[4], const __bf16* As, const __bf16* Bs, int kk) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-            av[i] = *(const bf16x8*)&As[(wm * 128 + i * 32 + (lane & 31)) * KSP + kk + 8 * (lane >> 5)];
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-            bv[j] = *(const bf16x8*)&Bs[(wn * 128 + j * 32 + (lane & 31)) * KSP + kk + 8 * (lane >> 5)];
-    };
-    auto mma16 = [&](const bf16x8 (&av)[4], const bf16x8 (&bv)[4]) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) acc[i][j] = mfma32(av[i], bv[j], acc[i][j]);
-    };
-    // One k slice from LDS stage `buf` while the next slice (registers ra, rb)
-    // is written to stage `sbuf`: the fragments of step kk + 16 are read while
-    // the MFMAs of step kk run, and the sixteen LDS writes are spread one per
-    // four MFMAs (scheduling groups), so the matrix cores never wait for a
-    // burst of writes.  Both stage indices are compile-time constants, which
-    // lets the compiler see that the writes and the reads do not overlap.
-    auto compute_stage = [&](auto buf_c, const u32x4 (&ra)[kChunks], const u32x4 (&rb)[kChunks], auto sbuf_c) {
-        constexpr int buf = decltype(buf_c)::value, sbuf = decltype(sbuf_c)::value;
+    load(0);
+    stage(0);
+    __syncthreads();
+    int buf = 0;
+    for (int k0 = 0; k0 < nk; k0 += KS) {
+        load(k0 + KS);                                     // next slice (clamped on the last)
+        __builtin_amdgcn_sched_barrier(0);                 // keep the loads ahead of the MFMAs
         const __bf16* As = smem + buf * kStage;
         const __bf16* Bs = As + BM * KSP;
-        bf16x8 a0[4], b0[4], a1[4], b1[4];
-        frags(a0, b0, As, Bs, 0);
-        frags(a1, b1, As, Bs, 16);
-        mma16(a0, b0);
-        frags(a0, b0, As, Bs, 32);
-        mma16(a1, b1);
-        frags(a1, b1, As, Bs, 48);
-        mma16(a0, b0);
-        mma16(a1, b1);
-        stage(ra, rb, sbuf);
-        __builtin_amdgcn_sched_group_barrier(0x100, 16, 0);        // fragments of steps 0 and 16
 #pragma unroll
-        for (int g = 0; g < 4; ++g) {
+        for (int kk = 0; kk < KS; kk += 16) {
+            bf16x8 av[4], bv[2];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                __builtin_amdgcn_sched_group_barrier(0x008, 4, 0);  // 4 MFMAs
-                __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);  // 1 LDS write of the next slice
-            }
-            if (g < 2) __builtin_amdgcn_sched_group_barrier(0x100, 8, 0);   // fragments of step 32 / 48
+            for (int i = 0; i < 4; ++i)
+                av[i] = *(const bf16x8*)&As[(wm * 128 + i * 32 + (lane & 31)) * KSP + kk + 8 * (lane >> 5)];
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                bv[j] = *(const bf16x8*)&Bs[(wn * 64 + j * 32 + (lane & 31)) * KSP + kk + 8 * (lane >> 5)];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) acc[i][j] = mfma32(av[i], bv[j], acc[i][j]);
         }
-    };
-    // Two LDS stages and two register sets: while slice s is multiplied from
-    // LDS, slice s + 1 (already in registers) is written to the other stage and
-    // slice s + 2 is in flight from memory.  nk is a multiple of 2 KS.  The
-    // last half-iteration stages a (clamped, valid) slice nobody reads.
-    using C0 = std::integral_constant<int, 0>;
-    using C1 = std::integral_constant<int, 1>;
-    u32x4 ra0[kChunks], rb0[kChunks], ra1[kChunks], rb1[kChunks];
-    load(ra0, rb0, 0);
-    load(ra1, rb1, KS);
-    stage(ra0, rb0, 0);
-    __syncthreads();
-    for (int k0 = 0; k0 < nk; k0 += 2 * KS) {
-        load(ra0, rb0, k0 + 2 * KS);
-        __builtin_amdgcn_sched_barrier(0);                 // keep the loads ahead of the MFMAs
-        compute_stage(C0{}, ra1, rb1, C1{});
+        stage(buf ^ 1);                                    // the last one stages a slice nobody reads
         __syncthreads();
-        load(ra1, rb1, k0 + 3 * KS);
-        __builtin_amdgcn_sched_barrier(0);
-        compute_stage(C1{}, ra0, rb0, C0{});
-        __syncthreads();
+        buf ^= 1;
     }
 }
 
@@ -186,7 +185,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm2_pack(Gemm2Args a) {
 }
 
 // G1: T_r[b][j n1 + a'] = sum_b' P16[r n1 + a', b'] V_j[b, b'].
-__global__ __launch_bounds__(kThreads) void k_gemm2_t(Gemm2Args a) {
+__global__ __launch_bounds__(kGT) void k_gemm2_t(Gemm2Args a) {
     __shared__ __attribute__((aligned(16))) __bf16 smem[2 * kStage];
     const int Mt = a.nrhs * (a.n1 / BM), Nt = a.J * (a.n2 / BN);
     const int L = xcd_linear(blockIdx.x, Mt * Nt);
@@ -207,22 +206,22 @@ __global__ __launch_bounds__(kThreads) void k_gemm2_t(Gemm2Args a) {
     const int64_t n2 = a.n2;
     const __bf16* Ab = a.P16 + m0 * n2;
     const __bf16* Bb = a.V + (int64_t)n0 * n2;
-    floatx16 acc[4][4];
+    floatx16 acc[4][2];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int jj = 0; jj < 4; ++jj) acc[i][jj] = floatx16{};
+        for (int jj = 0; jj < 2; ++jj) acc[i][jj] = floatx16{};
     gemm_tile(acc, a.n2, [&](int k0) { return Ab + k0; }, n2, [&](int k0) { return Bb + k0; }, n2, smem);
 
     // transposed bf16 store, one 32-column slice of the wave's sub-tile at a
     // time: FP32 staged in LDS as [column][row], then 8 rows per 16-byte store
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, wm = wave >> 1, wn = wave & 1;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, wm = wave >> 2, wn = wave & 3;
     const int64_t ldt = (int64_t)a.J * a.n1;
-    __bf16* Tb = a.T + ((int64_t)r * a.n2 + b0 + wn * 128) * ldt + (int64_t)j * a.n1 + a0 + wm * 128;
+    __bf16* Tb = a.T + ((int64_t)r * a.n2 + b0 + wn * 64) * ldt + (int64_t)j * a.n1 + a0 + wm * 128;
     constexpr int TP = 128 + 4;                            // staging pitch (floats)
     float* Ef = (float*)smem + wave * 32 * TP;             // [32 columns][128 rows]
 #pragma unroll
-    for (int jt = 0; jt < 4; ++jt) {
+    for (int jt = 0; jt < 2; ++jt) {
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -248,9 +247,9 @@ __global__ __launch_bounds__(kThreads) void k_gemm2_t(Gemm2Args a) {
 
 // G2: q_r[a, b] = sum_(j, a') U_j[a, a'] T_r[b][j n1 + a'] + (sigma2 + d) p_r[a, b],
 // with the CG epilogue's partial p.q and the step length alpha.
-__global__ __launch_bounds__(kThreads) void k_gemm2_y(Gemm2Args a) {
+__global__ __launch_bounds__(kGT) void k_gemm2_y(Gemm2Args a) {
     __shared__ __attribute__((aligned(16))) __bf16 smem[2 * kStage];
-    __shared__ double red[4];
+    __shared__ double red[8];
     const int tn = a.n2 / BN, tpr = (a.n1 / BM) * tn;
     const int L = xcd_linear(blockIdx.x, a.nrhs * tpr);
     const int r = L / tpr, t = L % tpr;
@@ -258,11 +257,11 @@ __global__ __launch_bounds__(kThreads) void k_gemm2_y(Gemm2Args a) {
     const int a0 = (t / tn) * BM, b0 = (t % tn) * BN;
     const int64_t n1 = a.n1, ldt = (int64_t)a.J * a.n1;
     const __bf16* Tr = a.T + ((int64_t)r * a.n2 + b0) * ldt;
-    floatx16 acc[4][4];
+    floatx16 acc[4][2];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int jj = 0; jj < 4; ++jj) acc[i][jj] = floatx16{};
+        for (int jj = 0; jj < 2; ++jj) acc[i][jj] = floatx16{};
     gemm_tile(acc, (int)ldt,
               [&](int k0) {
                   const int64_t j = k0 / n1;               // a 64-wide k slice never spans two terms
@@ -272,7 +271,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm2_y(Gemm2Args a) {
 
     // epilogue, one 32-column slice of the wave's sub-tile at a time, staged in
     // LDS so that p, d and q move as 16-byte vectors along rows
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, wm = wave >> 1, wn = wave & 1;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, wm = wave >> 2, wn = wave & 3;
     const int64_t n = n1 * a.n2;
     const bool cg = a.epi == EPI_CG;
     const float* Pr = (cg ? a.P : a.X) + (int64_t)r * n;
@@ -282,11 +281,11 @@ __global__ __launch_bounds__(kThreads) void k_gemm2_y(Gemm2Args a) {
     float* Ef = (float*)smem + wave * 128 * FP;            // [128 rows][32 columns]
     // chunk c of slice jj: row c*8 + lane/8, columns (lane % 8)*4 .. +3 of the slice;
     // the lane part of the offset is fixed, the rest uniform
-    const int64_t lane_e = (int64_t)(a0 + wm * 128 + (lane >> 3)) * a.n2 + b0 + wn * 128 + (lane & 7) * 4;
+    const int64_t lane_e = (int64_t)(a0 + wm * 128 + (lane >> 3)) * a.n2 + b0 + wn * 64 + (lane & 7) * 4;
     auto e_of = [&](int jj, int c) -> int64_t { return lane_e + (int64_t)(8 * c) * a.n2 + jj * 32; };
     double dacc[4] = {0.0, 0.0, 0.0, 0.0};                 // p.q in FP64, four short chains
 #pragma unroll
-    for (int jj = 0; jj < 4; ++jj) {
+    for (int jj = 0; jj < 2; ++jj) {
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -313,9 +312,9 @@ __global__ __launch_bounds__(kThreads) void k_gemm2_y(Gemm2Args a) {
     }
     const double dot = (dacc[0] + dacc[1]) + (dacc[2] + dacc[3]);
     if (!cg) return;
-    const double s = block_sum(dot, red);
+    const double s = block_sum8(dot, red);
     double tot;
-    if (last_block_reduce(s, a.partials + (int64_t)r * a.part_stride, a.counters + r, tpr, t, &tot, red) &&
+    if (last_block_reduce8(s, a.partials + (int64_t)r * a.part_stride, a.counters + r, tpr, t, &tot, red) &&
         threadIdx.x == 0) {
         CgState& st = a.cg[r];
         if (!(tot > 0.0) || !finite_d(tot)) {
@@ -349,10 +348,10 @@ hipError_t launch_gemm2(const Gemm2Args& a, int stage, hipStream_t s) {
         else hipLaunchKernelGGL(k_gemm2_pack<false>, grid, dim3(kThreads), 0, s, a);
     } else if (stage == 1) {
         const int64_t T = (int64_t)a.nrhs * (a.n1 / BM) * a.J * (a.n2 / BN);
-        hipLaunchKernelGGL(k_gemm2_t, dim3((unsigned)T), dim3(kThreads), 0, s, a);
+        hipLaunchKernelGGL(k_gemm2_t, dim3((unsigned)T), dim3(kGT), 0, s, a);
     } else {
         const int64_t T = (int64_t)a.nrhs * gemm2_blocks_per_rhs(a.n1, a.n2);
-        hipLaunchKernelGGL(k_gemm2_y, dim3((unsigned)T), dim3(kThreads), 0, s, a);
+        hipLaunchKernelGGL(k_gemm2_y, dim3((unsigned)T), dim3(kGT), 0, s, a);
     }
     return hipGetLastError();
 }
