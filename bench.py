@@ -44,7 +44,11 @@ FP32_MFMA_PEAK_TFLOPS = 157.3
 #   contract_mid  : read T, write T'                                        2 words
 #   contract_last : read T', r, p_old, write q, p_new                       5 words
 #   update        : read x, r, p, q, write x, r                             6 words
-BYTES_PER_ELEM = {"slab23": 12, "contract_rows": 12, "contract_mid": 8, "contract_last": 20, "update": 24}
+# algorithmic bytes per element and RHS*iteration of each c2 launch class (FP32): slab23 reads r, p and
+# writes T; contract_last reads T, p, r and writes q, p; update reads x, p, r, q and writes x, r; the
+# fused persistent CG reads r, p, x and writes p, T, x (phase A), reads T, p (B), reads and writes r (C)
+BYTES_PER_ELEM = {"slab23": 12, "contract_rows": 12, "contract_mid": 8, "contract_last": 20, "update": 24,
+                  "cg_fused": 40}
 
 
 def parse():
@@ -380,9 +384,11 @@ def run_counters(args):
     torch.cuda.synchronize()
     b.copy_(a)                        # runtime copy kernel: the marker that ends the set-up phase
     torch.cuda.synchronize()
-    iters = args.max_iters or 48
+    # c2: one chunk of 32 iterations, i.e. one launch of the fused persistent CG (it needs host checks)
+    iters = args.max_iters or (COUNTERS_C2_ITERS if name == "c2" else 48)
     # inner_tol 1e-30: no reliable update falls due this early, so every launch has all RHS active
-    _, info = op.solve(B, nrhs, tol=tol, max_iters=iters, prec=prec, inner_tol=1e-30, check_every=0)
+    _, info = op.solve(B, nrhs, tol=tol, max_iters=iters, prec=prec, inner_tol=1e-30,
+                       check_every=32 if name == "c2" else 0)
     torch.cuda.synchronize()
     from paper_2309_03060_amd import decode_info
     rhs_iters = sum(r["iters"] for r in decode_info(info, nrhs))
@@ -394,14 +400,29 @@ def run_counters(args):
 # --- rocprofv3 counter summaries ---------------------------------------------------------------
 COPY_REF_WORDS = 64 << 20            # the counters run's reference copy: 256 MiB read + 256 MiB written
 PMC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+COUNTERS_C2_ITERS = 32               # c2 counters run: one fused launch of 32 iterations x 32 RHS
 KERNEL_SOURCES = {                   # files each launch class is compiled from (counters go stale with them)
     "contract": ["contract.hip", "contract.h", "common.h"],
     "slab23": ["slab.hip", "slab.h", "common.h"],
     "update": ["vector.hip", "vector.h", "common.h"],
+    "cg_fused": ["fused.hip", "fused.h", "common.h"],
 }
 # bench launch-class name of each counter class, per workload (c2 fuses modes 2 and 3 in the slab pass,
-# so its only column-layout FP32 contraction is the last mode)
-BENCH_CLASS = {"c2": {"contract_cols_f32": "contract_last", "slab23_f32": "slab23", "update_float": "update"}}
+# so its only column-layout FP32 contraction is the last mode; the fused persistent CG replaces all three)
+BENCH_CLASS = {"c2": {"contract_cols_f32": "contract_last", "slab23_f32": "slab23", "update_float": "update",
+                      "k_fused_cg": "cg_fused"}}
+# RHS*iterations one dispatch of a counter class covers in the counters run (default: one iteration of
+# every right-hand side)
+RHS_ITERS_PER_DISPATCH = {("c2", "k_fused_cg"): COUNTERS_C2_ITERS * 32}
+
+
+def source_kind(cls):
+    """KERNEL_SOURCES key of a counter or bench launch class."""
+    if cls.startswith("contract"):
+        return "contract"
+    if cls in ("k_fused_cg", "cg_fused"):
+        return "cg_fused"
+    return cls.split("_")[0]
 
 
 def kernel_class(name):
@@ -477,10 +498,11 @@ def pmc_summary(csvs, workload, out_json):
             mb = byt / 1e6
             bench = BENCH_CLASS.get(workload, {}).get(c)
             if bench:
-                kind = "contract" if c.startswith("contract") else c.split("_")[0]
                 record[bench] = {"bytes_per_launch_all_rhs_active": round(byt),
                                  "fetch_kib": round(avg["FETCH_SIZE"], 1), "write_kib": round(avg["WRITE_SIZE"], 1),
-                                 "sources_sha1": sources_digest(kind)}
+                                 "sources_sha1": sources_digest(source_kind(c))}
+                if (workload, c) in RHS_ITERS_PER_DISPATCH:
+                    record[bench]["rhs_iters_per_dispatch"] = RHS_ITERS_PER_DISPATCH[(workload, c)]
         n = max(len(v) for v in d.values())
         du = sum(dur[c]) / len(dur[c]) if dur[c] else float("nan")
         lines.append(f"| {c} | {n} | {du:.1f} | " + " | ".join(
@@ -517,16 +539,17 @@ def trace_summary(prefix, cmd, title):
 
 
 def measured_traffic(workload, kernel, nrhs, rhs_iters, launches):
-    """HBM bytes per launch from the committed counter record, scaled to the average number of active
-    right-hand sides per launch; None when there is no record or the kernel's sources changed since."""
+    """HBM bytes per launch from the committed counter record, scaled to the average number of
+    RHS*iterations per launch (a fused launch covers many iterations); None when there is no record or
+    the kernel's sources changed since."""
     try:
         rec = json.load(open(PMC_FILE))[workload]["kernels"][kernel]
     except (OSError, KeyError, ValueError):
         return None
-    kind = "contract" if kernel.startswith("contract") else kernel
-    if rec.get("sources_sha1") != sources_digest(kind):
+    if rec.get("sources_sha1") != sources_digest(source_kind(kernel)):
         return None
-    return int(rec["bytes_per_launch_all_rhs_active"] * (rhs_iters / launches) / nrhs)
+    per_rhs_iter = rec["bytes_per_launch_all_rhs_active"] / rec.get("rhs_iters_per_dispatch", nrhs)
+    return int(per_rhs_iter * rhs_iters / launches)
 
 
 def main():
@@ -634,6 +657,18 @@ def main():
                           "status": sorted({r["status"] for r in rec})}
             progress(f"time-to-solution {label}: {res[label]['seconds']} s")
         res["speedup"] = round(res["fp64_cg"]["seconds"] / res["mixed_fp32_reliable"]["seconds"], 3)
+        # the same mixed solve on the separate-kernel path (slab23 / contract_last / update per iteration)
+        op.set_engine("fused_cg", False)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        X, info = op.solve(B, nrhs, **dict(opts, tol=1e-6))
+        torch.cuda.synchronize()
+        rec = decode_info(info, nrhs)
+        res["mixed_fp32_reliable_separate_kernels"] = {
+            "seconds": round(time.perf_counter() - t1, 4), "iters_max": max(r["iters"] for r in rec),
+            "relres_max": max(r["relres"] for r in rec), "status": sorted({r["status"] for r in rec})}
+        op.set_engine("fused_cg", True)
+        progress("time-to-solution on the separate-kernel path done")
         res["direct_eig_solve"] = direct_solve(op, B, nrhs, n, res["mixed_fp32_reliable"]["seconds"])
         res["note"] = ("fp64_cg relres is its recursive residual; mixed relres is the FP64 true residual; "
                        "speedup = fp64_cg seconds / mixed_fp32_reliable seconds")

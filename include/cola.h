@@ -190,12 +190,28 @@ int32_t cola_eig_solve(cola_op_t op, const double* B, double* X, int32_t nrhs, v
  * `stream` (synchronises it).  Optional: without it a fixed default is used. */
 int32_t cola_autotune(cola_op_t op, int32_t nrhs, void* stream);
 
+/* Engine switches.  Every engine is on by default and is used wherever its
+ * shape conditions hold; switched off, the op uses the general per-mode
+ * contraction path for those shapes instead (the same arithmetic up to
+ * rounding order: for comparing engines and testing the general path).
+ * Synchronises the device and drops captured chunk graphs.  Returns
+ * COLA_ERR_INVALID_ARG for an unknown engine. */
+#define COLA_ENGINE_FUSED_CG 1  /* persistent CG, one cooperative launch per chunk of iterations:
+                                   one-term K1 (x) K2 (x) K3 (+ diag) with 64-wide modes, FP32
+                                   working precision, solves with check_every > 0               */
+#define COLA_ENGINE_GEMM2    2  /* dense-GEMM MVM: BF16, two-mode, modes multiples of 256       */
+#define COLA_ENGINE_GEMM3    3  /* dense-GEMM MVM: FP32, one-term three-mode, 256-wide modes    */
+#define COLA_ENGINE_SLAB     4  /* fused mode-2/mode-3 products of three-mode terms, modes <= 64 */
+#define COLA_ENGINE_RESIDENT 5  /* resident batched CG of many small two-mode systems           */
+int32_t cola_op_set_engine(cola_op_t op, int32_t engine, int32_t enable);
+
 /* Per-kernel timing with HIP events recorded on the launch stream around
  * every kernel of the named class.  Classes: "slab23" (fused modes 2-3 of
  * three-mode terms), "contract_rows" (last mode), "contract_mid" (middle
  * mode), "contract_last" (first mode, with the diagonal term and the CG
  * epilogue), "update" (x, r update and residual norm), "resident" (batched
- * small systems); the same names with "_fp64" for launches in FP64 (plain
+ * small systems), "cg_fused" (one launch of the persistent CG: a chunk of
+ * iterations for a batch of right-hand sides); the same names with "_fp64" for launches in FP64 (plain
  * FP64 solves and the FP64 residuals of mixed precision).  enable != 0
  * starts collecting (and clears totals). */
 int32_t cola_profile_enable(cola_op_t op, int32_t enable);

@@ -33,12 +33,14 @@ COLA_REFINE_RELIABLE = 0
 COLA_REFINE_RESTART = 1
 REFINE_BY_NAME = {"reliable": COLA_REFINE_RELIABLE, "restart": COLA_REFINE_RESTART}
 
+ENGINE_BY_NAME = {"fused_cg": 1, "gemm2": 2, "gemm3": 3, "slab": 4, "resident": 5}
+
 PREC_BY_NAME = {"fp64": COLA_PREC_FP64, "fp32": COLA_PREC_FP32,
                 "bf16": COLA_PREC_BF16, "bf16x3": COLA_PREC_BF16X3}
 
 EXPORTED = ("cola_op_create", "cola_op_destroy", "cola_op_size", "cola_kron_matvec",
             "cola_cg_solve", "cola_cg_solve_backward", "cola_eig_solve", "cola_autotune",
-            "cola_profile_enable", "cola_profile_read", "cola_status_string")
+            "cola_op_set_engine", "cola_profile_enable", "cola_profile_read", "cola_status_string")
 
 
 class SystemDesc(ctypes.Structure):
@@ -85,6 +87,7 @@ def lib():
                                              ctypes.POINTER(vp), ctypes.POINTER(vp), vp, vp, vp]
         L.cola_eig_solve.argtypes = [vp, vp, vp, i32, vp]
         L.cola_autotune.argtypes = [vp, i32, vp]
+        L.cola_op_set_engine.argtypes = [vp, i32, i32]
         L.cola_profile_enable.argtypes = [vp, i32]
         L.cola_profile_read.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(dbl), ctypes.POINTER(i64)]
         L.cola_status_string.argtypes = [i32]

@@ -12,6 +12,7 @@
 
 #include "gemm.h"
 #include "eig.h"
+#include "fused.h"
 #include "gemm3.h"
 #include "grad.h"
 #include "op.h"
@@ -437,6 +438,96 @@ int32_t capture_chunk(cola_op_s* op, const SysInfo& s, int prec, int nrhs, T* x,
     return COLA_OK;
 }
 
+// Fused-CG workspace: group sums, barrier counters and the time-out flag
+// (allocated on the first fused solve; sized for every co-resident block).
+int32_t ensure_fused(cola_op_s* op) {
+    if (op->fused_max_blocks < 0) op->fused_max_blocks = fused_cg_max_blocks();
+    if (op->fused_max_blocks < 8) return COLA_ERR_UNSUPPORTED;
+    if (op->fused_bar) return COLA_OK;
+    const int mb = op->fused_max_blocks;
+    const size_t bar_bytes = sizeof(uint32_t) * ((size_t)mb * kFusedBarStride + 1);
+    int32_t rc = alloc_bytes((void**)&op->fused_partials, sizeof(double) * 2 * (size_t)mb);
+    if (rc == COLA_OK) rc = alloc_bytes((void**)&op->fused_bar, bar_bytes);
+    for (int b = 0; b < 2 && rc == COLA_OK; ++b)
+        if (hipEventCreateWithFlags(&op->fused_done[b], hipEventDisableTiming) != hipSuccess) rc = COLA_ERR_HIP;
+    if (rc == COLA_OK && hipMemset(op->fused_bar, 0, bar_bytes) != hipSuccess) rc = COLA_ERR_HIP;
+    if (rc != COLA_OK) {               // leave the path off rather than half set up
+        (void)hipGetLastError();
+        if (op->fused_partials) (void)hipFree(op->fused_partials);
+        if (op->fused_bar) (void)hipFree(op->fused_bar);
+        op->fused_partials = nullptr;
+        op->fused_bar = nullptr;
+        op->fused_max_blocks = 0;
+    }
+    return rc;
+}
+
+bool fused_eligible(const cola_op_s* op, const SysInfo& s, int prec, int check_every) {
+    return op->use_fused && check_every > 0 && op->fused_max_blocks != 0 && prec == op->prec &&
+           fused_cg_supported(prec, s.Fv, s.J, s.dims);
+}
+
+// CG iterations of a one-term three-mode FP32 operator with 64-wide modes:
+// every chunk of check_every iterations is one cooperative launch per batch of
+// right-hand sides (then the reliable-update tail), with the host reading the
+// count of active right-hand sides one chunk behind, as in the graph path.
+int32_t run_cg_fused(cola_op_s* op, const SysInfo& s, int nrhs, float* x, float* r, float* p, int max_iters,
+                     int check_every, const ReliableTail* tail, hipStream_t st) {
+    Workspace& w = op->ws;
+    const int chunk = std::min(check_every, max_iters);
+    const int nchunks = (max_iters + chunk - 1) / chunk;
+    const int bpr = fused_cg_blocks_per_rhs(nrhs, op->fused_max_blocks);
+    const int per_launch = op->fused_max_blocks / bpr;
+    const int64_t n = s.n;
+    FusedCgArgs a{};
+    a.bpr = bpr;
+    a.iters = chunk;
+    a.K1 = op->fac32 + s.fac_off[0];
+    a.K2 = op->fac32 + s.fac_off[1];
+    a.K3 = op->fac32 + s.fac_off[2];
+    a.dvec = s.diag_off >= 0 ? op->diag32 + s.diag_off : nullptr;
+    a.sigma2 = s.sigma2;
+    a.partials = op->fused_partials;
+    a.bar = op->fused_bar;
+    a.err = op->fused_bar + (size_t)op->fused_max_blocks * kFusedBarStride;
+    a.cnt = w.cnt;
+    float* t = (float*)w.inter[0];
+    int last = -1;
+    for (int c = 0; c < nchunks; ++c) {
+        for (int g0 = 0; g0 < nrhs; g0 += per_launch) {
+            a.nrhs = std::min(per_launch, nrhs - g0);
+            a.x = x + g0 * n;
+            a.r = r + g0 * n;
+            a.p = p + g0 * n;
+            a.T = t + g0 * n;
+            a.cg = w.cg + g0;
+            HIP_TRY(fill_i32((int32_t*)op->fused_bar, 0, (int64_t)a.nrhs * kFusedBarStride, st));
+            ProfScope ps(op->prof, "cg_fused", st);
+            HIP_TRY(launch_fused_cg(a, st));
+        }
+        if (tail) {
+            int32_t rc = enqueue_tail(op, s, nrhs, *tail, false, st);
+            if (rc != COLA_OK) return rc;
+        }
+        const int b = c & 1;
+        HIP_TRY(hipMemcpyAsync(&w.host_flag[b], &w.cnt->num_active, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipEventRecord(op->fused_done[b], st));
+        last = c;
+        if (c >= 1) {
+            HIP_TRY(hipEventSynchronize(op->fused_done[(c - 1) & 1]));
+            if (*(volatile int32_t*)&w.host_flag[(c - 1) & 1] <= 0) break;
+        }
+    }
+    if (last >= 0) HIP_TRY(hipEventSynchronize(op->fused_done[last & 1]));
+    uint32_t timed_out = 0;
+    HIP_TRY(hipMemcpy(&timed_out, a.err, sizeof(uint32_t), hipMemcpyDeviceToHost));
+    if (timed_out) {
+        op->use_fused = false;         // a group never met: report it and stop using the path
+        return COLA_ERR_HIP;
+    }
+    return COLA_OK;
+}
+
 // CG iterations.  check_every == 0: enqueue max_iters iterations directly
 // (no host wait; safe under the caller's stream capture).  Otherwise the
 // iterations run as replays of two captured chunk graphs of check_every
@@ -448,6 +539,10 @@ template <typename T>
 int32_t run_cg(cola_op_s* op, const SysInfo& s, int prec, int nrhs, T* x, T* r, T* p, T* q, int max_iters,
                int check_every, const ReliableTail* tail, hipStream_t st) {
     Workspace& w = op->ws;
+    if constexpr (sizeof(T) == 4) {
+        if (fused_eligible(op, s, prec, check_every) && ensure_fused(op) == COLA_OK)
+            return run_cg_fused(op, s, nrhs, x, r, p, max_iters, check_every, tail, st);
+    }
     const int chunk = check_every > 0 ? std::min(check_every, max_iters) : (tail ? std::min(32, max_iters) : max_iters);
     const int nchunks = (max_iters + chunk - 1) / chunk;
     auto direct_chunk = [&]() -> int32_t {
@@ -996,8 +1091,10 @@ int32_t cola_op_destroy(cola_op_t op) {
     free_ws(op->ws);
     if (op->eig_qt) cola_op_destroy(op->eig_qt);
     if (op->eig_q) cola_op_destroy(op->eig_q);
+    for (hipEvent_t e : op->fused_done)
+        if (e) (void)hipEventDestroy(e);
     void* ptrs[] = {op->fac64, op->fac32, op->facbf, op->diag64, op->diag32, op->grad_buf, op->eig_lam,
-                    op->eig_tmp};
+                    op->eig_tmp, op->fused_partials, op->fused_bar};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     delete op;
@@ -1069,6 +1166,22 @@ int32_t cola_cg_solve_backward(cola_op_t op, const double* X, const double* G, i
                          ddiag ? ddiag[i] : nullptr, dsigma2 ? dsigma2 + i : nullptr, st);
         if (rc != COLA_OK) return rc;
     }
+    return COLA_OK;
+}
+
+int32_t cola_op_set_engine(cola_op_t op, int32_t engine, int32_t enable) {
+    if (!op) return COLA_ERR_INVALID_ARG;
+    const bool on = enable != 0;
+    switch (engine) {
+        case COLA_ENGINE_FUSED_CG: op->use_fused = on; break;
+        case COLA_ENGINE_GEMM2: op->use_gemm2 = on; break;
+        case COLA_ENGINE_GEMM3: op->use_gemm3 = on; break;
+        case COLA_ENGINE_SLAB: op->use_slab = on; break;
+        case COLA_ENGINE_RESIDENT: op->use_resident = on; break;
+        default: return COLA_ERR_INVALID_ARG;
+    }
+    (void)hipDeviceSynchronize();
+    destroy_graphs(op);              // captured chunks embed the previous choice
     return COLA_OK;
 }
 

@@ -122,6 +122,11 @@ struct cola_op_s {
     bool use_slab = true;           // fuse modes 2 and 3 of three-mode terms when slabs fit in LDS
     bool use_gemm2 = true;          // BF16 two-mode operators with large modes: dense-GEMM MVM
     bool use_gemm3 = true;          // FP32 one-term three-mode operators with 256-wide modes: dense-GEMM MVM
+    bool use_fused = true;          // FP32 one-term three-mode operators with 64-wide modes: persistent fused CG
+    int fused_max_blocks = -1;      // co-resident fused-CG blocks (-1: not yet queried)
+    double* fused_partials = nullptr;   // fused-CG group sums (2 * fused_max_blocks)
+    uint32_t* fused_bar = nullptr;      // fused-CG barrier counters, then the time-out flag
+    hipEvent_t fused_done[2] = {nullptr, nullptr};
     bool resident_ok = false;       // every system fits the resident batched kernel
     bool use_resident = true;
     int num_cus = 0;

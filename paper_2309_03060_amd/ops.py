@@ -197,6 +197,13 @@ class KronOperator:
     def autotune(self, nrhs: int):
         L.check("cola_autotune", self.lib.cola_autotune(self.handle, nrhs, _stream_ptr()))
 
+    def set_engine(self, name: str, enable: bool):
+        """Switch one kernel engine on or off ("fused_cg", "gemm2", "gemm3", "slab", "resident")."""
+        if name not in L.ENGINE_BY_NAME:
+            raise ValueError(f"unknown engine {name!r}; one of {sorted(L.ENGINE_BY_NAME)}")
+        L.check("cola_op_set_engine",
+                self.lib.cola_op_set_engine(self.handle, L.ENGINE_BY_NAME[name], 1 if enable else 0))
+
     def profile_enable(self, on: bool = True):
         L.check("cola_profile_enable", self.lib.cola_profile_enable(self.handle, 1 if on else 0))
 

@@ -69,3 +69,18 @@ def test_measured_traffic_follows_active_rhs_and_sources(tmp_path, monkeypatch):
     rec["c2"]["kernels"]["update"]["sources_sha1"] = "stale"
     path.write_text(json.dumps(rec))
     assert bench.measured_traffic("c2", "update", 32, 160, 10) is None
+
+
+def test_measured_traffic_of_multi_iteration_launches(tmp_path, monkeypatch):
+    """A fused launch record covers rhs_iters_per_dispatch RHS*iterations; traffic per launch follows the
+    RHS*iterations the timed launches actually carried."""
+    rec = {"c2": {"scale": {}, "kernels": {"cg_fused": {"bytes_per_launch_all_rhs_active": 1024 * 400,
+                                                        "rhs_iters_per_dispatch": 1024,
+                                                        "sources_sha1": bench.sources_digest("cg_fused")}}}}
+    path = tmp_path / "t.json"
+    path.write_text(json.dumps(rec))
+    monkeypatch.setattr(bench, "PMC_FILE", str(path))
+    # 4 launches carrying 2048 RHS*iterations: 512 each at 400 bytes
+    assert bench.measured_traffic("c2", "cg_fused", 32, 2048, 4) == 512 * 400
+    assert bench.source_kind("k_fused_cg") == "cg_fused" and bench.source_kind("contract_cols_f32") == "contract"
+    assert bench.kernel_class("cola::(anonymous namespace)::k_fused_cg<2>(cola::FusedCgArgs)") == "k_fused_cg"
