@@ -503,7 +503,16 @@ int32_t run_cg_fused(cola_op_s* op, const SysInfo& s, int nrhs, float* x, float*
             a.cg = w.cg + g0;
             HIP_TRY(fill_i32((int32_t*)op->fused_bar, 0, (int64_t)a.nrhs * kFusedBarStride, st));
             ProfScope ps(op->prof, "cg_fused", st);
-            HIP_TRY(launch_fused_cg(a, st));
+            const hipError_t le = launch_fused_cg(a, st);
+            if (le != hipSuccess) {
+                (void)hipGetLastError();
+                // refused before any iteration ran: the caller continues on the separate-kernel path
+                if (c == 0 && g0 == 0) {
+                    op->use_fused = false;
+                    return COLA_ERR_UNSUPPORTED;
+                }
+                return COLA_ERR_HIP;
+            }
         }
         if (tail) {
             int32_t rc = enqueue_tail(op, s, nrhs, *tail, false, st);
@@ -540,8 +549,10 @@ int32_t run_cg(cola_op_s* op, const SysInfo& s, int prec, int nrhs, T* x, T* r, 
                int check_every, const ReliableTail* tail, hipStream_t st) {
     Workspace& w = op->ws;
     if constexpr (sizeof(T) == 4) {
-        if (fused_eligible(op, s, prec, check_every) && ensure_fused(op) == COLA_OK)
-            return run_cg_fused(op, s, nrhs, x, r, p, max_iters, check_every, tail, st);
+        if (fused_eligible(op, s, prec, check_every) && ensure_fused(op) == COLA_OK) {
+            const int32_t rc = run_cg_fused(op, s, nrhs, x, r, p, max_iters, check_every, tail, st);
+            if (rc != COLA_ERR_UNSUPPORTED) return rc;
+        }
     }
     const int chunk = check_every > 0 ? std::min(check_every, max_iters) : (tail ? std::min(32, max_iters) : max_iters);
     const int nchunks = (max_iters + chunk - 1) / chunk;

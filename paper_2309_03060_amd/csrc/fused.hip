@@ -52,6 +52,14 @@ __device__ inline floatx4 ldc(__amdgpu_buffer_rsrc_t rs, int lane_e, int uni_e) 
 __device__ inline void stc(__amdgpu_buffer_rsrc_t rs, int lane_e, int uni_e, floatx4 v) {
     __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(uintx4, v), rs, lane_e * 4, uni_e * 4, kSC1);
 }
+// The same through the ordinary cache path, for data only this block touches
+// (x) or nobody writes (the diagonal); a resource of zero records reads zeros.
+__device__ inline floatx4 ldn(__amdgpu_buffer_rsrc_t rs, int lane_e, int uni_e) {
+    return __builtin_bit_cast(floatx4, __builtin_amdgcn_raw_buffer_load_b128(rs, lane_e * 4, uni_e * 4, 0));
+}
+__device__ inline void stn(__amdgpu_buffer_rsrc_t rs, int lane_e, int uni_e, floatx4 v) {
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(uintx4, v), rs, lane_e * 4, uni_e * 4, 0);
+}
 __device__ inline floatx4 mma(float a, float b, floatx4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
@@ -69,11 +77,15 @@ __device__ inline double block_sum16(double v, double* red) {
     return s;
 }
 
-// Arrive at the group barrier once every wave's stores have completed, then
-// wait for the other blocks of the group.  Returns false in every thread of
-// the block after a time-out (the flag is set; the launch is then void).
+// This wave's memory operations have completed (stores included): issued by
+// every wave that stored data other blocks read after the next barrier.
+__device__ inline void fence_stores() { __builtin_amdgcn_s_waitcnt(0); }
+
+// Group barrier: thread 0 arrives once the whole block is here, then waits for
+// the other blocks of the group.  Loads in flight stay in flight (a block
+// barrier waits for LDS operations only).  Returns false in every thread of the
+// block after a time-out (the flag is set; the launch is then void).
 __device__ inline bool group_wait(uint32_t* ctr, uint32_t target, uint32_t* err, int* s_ok) {
-    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (threadIdx.x == 0) {
         __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -98,7 +110,10 @@ __device__ inline bool group_wait(uint32_t* ctr, uint32_t target, uint32_t* err,
 __device__ inline bool group_sum(double v, double* slots, int bpr, int rank, uint32_t* ctr, uint32_t target,
                                  uint32_t* err, double* red, double* s_tot, int* s_ok) {
     const double part = block_sum16(v, red);
-    if (threadIdx.x == 0) store_coherent(slots + rank, part);
+    if (threadIdx.x == 0) {
+        store_coherent(slots + rank, part);
+        fence_stores();
+    }
     if (!group_wait(ctr, target, err, s_ok)) return false;
     if (threadIdx.x == 0) {
         double t = 0.0;
@@ -149,11 +164,12 @@ __global__ __launch_bounds__(kFT) void k_fused_cg(FusedCgArgs a) {
         fs.pending = 0;
     }
 
-    float* X = a.x + (int64_t)grp * NV;
+    const auto rsX = vec_rsrc(a.x + (int64_t)grp * NV);
+    const auto rsD = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(a.dvec), (short)0,
+                                                       a.dvec ? NV * 4 : 0, 0x00020000);
     const auto rsR = vec_rsrc(a.r + (int64_t)grp * NV);
     const auto rsP = vec_rsrc(a.p + (int64_t)grp * NV);
     const auto rsT = vec_rsrc(a.T + (int64_t)grp * NV);
-    const float* dv = a.dvec;
     const float s2 = (float)a.sigma2;
     double* slotsB = a.partials + (int64_t)grp * a.bpr;
     double* slotsC = a.partials + (int64_t)(a.nrhs + grp) * a.bpr;
@@ -166,7 +182,6 @@ __global__ __launch_bounds__(kFT) void k_fused_cg(FusedCgArgs a) {
         K2s[rr * PD + c] = a.K2[e];
         K3s[rr * PD + c] = a.K3[e];
     }
-    __syncthreads();
 
     const int u0 = (rank * 4 + quad) * SPQ;          // this quad's first slab / strip
     float* Wt = Wq[quad];
@@ -174,12 +189,36 @@ __global__ __launch_bounds__(kFT) void k_fused_cg(FusedCgArgs a) {
     // at step s = 4 u + c is column 16 u + 4 lq + c (4 consecutive columns per lane)
     const int arow = 16 * qw + lr;
     const int alane = arow * D + 4 * lq;            // + 16 u: this lane's elements of a slab
-    // phases B, C: row qt / 4 of the strip, columns 16 u + 4 (qt % 4) + c
-    const int brow = qt >> 2, bsub = qt & 3;
-    const int blane = brow * (D * D) + 4 * bsub;    // + 16 u: this lane's elements of a strip
     // T write-out: float4 number qt + 256 q of a slab is row qt / 16 + 16 q, column 4 (qt % 16)
     const int tlane = (qt >> 4) * D + 4 * (qt & 15);
     const int tlds = (qt >> 4) * PD + 4 * (qt & 15);
+    // phase B staging of a T strip: row qt / 4, columns 16 u + 4 (qt % 4) + c
+    const int brow = qt >> 2, bsub = qt & 3;
+    const int blane = brow * (D * D) + 4 * bsub;    // + 16 u (+ strip column c0)
+    // phases B, C output roles: the transposed product Q^T = T^T K1^T puts 4 consecutive
+    // columns of one output row in each lane; tile (ti, tj) of wave (wm, wn) holds row
+    // 32 wn + 16 tj + lr, columns c0 + 32 wm + 16 ti + 4 lq + v
+    const int olane = (32 * wn + lr) * (D * D) + 32 * wm + 4 * lq;   // + 16 ti (+ c0 + 16 D^2 tj)
+
+    float pv[16], rv[16];                            // phase A operands of the current slab
+    auto load_p = [&](int sl) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const floatx4 pp = ldc(rsP, alane + 16 * u, sl * SL);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) pv[4 * u + c] = pp[c];
+        }
+    };
+    auto load_r = [&](int sl) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const floatx4 r4 = ldc(rsR, alane + 16 * u, sl * SL);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) rv[4 * u + c] = r4[c];
+        }
+    };
+    load_p(u0);
+    __syncthreads();                                 // factors staged, state initialised
 
     for (int it = 0; it < a.iters; ++it) {
         // ---------------- phase A ----------------
@@ -189,36 +228,16 @@ __global__ __launch_bounds__(kFT) void k_fused_cg(FusedCgArgs a) {
             const double beta = fs.beta;
             const float aprev = (float)fs.alpha;
             const bool pend = fs.pending != 0;
-            float pv[16], rv[16], xv[16];
-            auto load_slab = [&](int sl) {
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const floatx4 pp = ldc(rsP, alane + 16 * u, sl * SL), r4 = ldc(rsR, alane + 16 * u, sl * SL);
-                    const floatx4 x4 = *(const floatx4*)(X + sl * SL + alane + 16 * u);
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) {
-                        pv[4 * u + c] = pp[c];
-                        rv[4 * u + c] = r4[c];
-                        xv[4 * u + c] = x4[c];
-                    }
-                }
-            };
-            load_slab(u0);
+            load_r(u0);                              // p of the first slab is in flight already
 #pragma unroll
             for (int s = 0; s < SPQ; ++s) {
                 const int sl = u0 + s;
+                floatx4 xv[4];                         // x arrives during the first product
+#pragma unroll
+                for (int u = 0; u < 4; ++u) xv[u] = ldn(rsX, alane + 16 * u, sl * SL);
                 float av[16];
 #pragma unroll
                 for (int q = 0; q < 16; ++q) av[q] = pnew_of(rv[q], pv[q], beta);
-                if (pend) {
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        floatx4 x4;
-#pragma unroll
-                        for (int c = 0; c < 4; ++c) x4[c] = __builtin_fmaf(aprev, pv[4 * u + c], xv[4 * u + c]);
-                        *(floatx4*)(X + sl * SL + alane + 16 * u) = x4;
-                    }
-                }
 #pragma unroll
                 for (int u = 0; u < 4; ++u)
                     stc(rsP, alane + 16 * u, sl * SL, floatx4{av[4 * u], av[4 * u + 1], av[4 * u + 2], av[4 * u + 3]});
@@ -231,7 +250,18 @@ __global__ __launch_bounds__(kFT) void k_fused_cg(FusedCgArgs a) {
 #pragma unroll
                     for (int j = 0; j < 4; ++j) acc1[j] = mma(av[st], K3s[(16 * j + lr) * PD + kcol], acc1[j]);
                 }
-                if (s + 1 < SPQ) load_slab(sl + 1);        // next slab in flight during the second product
+                if (pend) {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) xv[u][c] = __builtin_fmaf(aprev, pv[4 * u + c], xv[u][c]);
+                        stn(rsX, alane + 16 * u, sl * SL, xv[u]);
+                    }
+                }
+                if (s + 1 < SPQ) {                     // next slab in flight during the second product
+                    load_p(sl + 1);
+                    load_r(sl + 1);
+                }
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
 #pragma unroll
@@ -272,66 +302,86 @@ __global__ __launch_bounds__(kFT) void k_fused_cg(FusedCgArgs a) {
             }
         }
         if (tid == 0) fs.pending = 0;
+        fence_stores();                                        // p and T visible to the group
         target += a.bpr;
         if (!group_wait(ctr, target, a.err, &s_ok)) return;
 
         // ---------------- phase B ----------------
-        // q = K1 T + (sigma2 + d) p per strip; q stays in registers for phase C
-        float qh[SPQ][16];
+        // q = K1 T + (sigma2 + d) p per strip, computed transposed so each lane holds
+        // 16-byte runs of q; q stays in registers for phase C
+        floatx4 qh[SPQ][2][2];
+        floatx4 rh[SPQ][2][2];
         double dot = 0.0;
+        {
+            floatx4 tv[4], pb[2][2];
+            auto load_strip = [&](int s, floatx4* tv_, floatx4 (*pb_)[2]) {
+                const int c0 = (u0 + s) * D;
 #pragma unroll
-        for (int s = 0; s < SPQ; ++s) {
-            const int c0 = (u0 + s) * D;
-            float ph[16];
+                for (int u = 0; u < 4; ++u) tv_[u] = ldc(rsT, blane + 16 * u, c0);
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const floatx4 t4 = ldc(rsT, blane + 16 * u, c0), p4 = ldc(rsP, blane + 16 * u, c0);
-                *(floatx4*)(Wt + brow * PD + 16 * u + 4 * bsub) = t4;
+                for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
-                for (int c = 0; c < 4; ++c) ph[4 * u + c] = p4[c];
-            }
-            __syncthreads();                                   // T strip staged
-            floatx4 acc[2][2];
+                    for (int tj = 0; tj < 2; ++tj) pb_[ti][tj] = ldc(rsP, olane + 16 * ti, c0 + 16 * SL * tj);
+            };
+            load_strip(0, tv, pb);
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
+            for (int s = 0; s < SPQ; ++s) {
+                const int c0 = (u0 + s) * D;
 #pragma unroll
-                for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0, 0, 0, 0};
-#pragma unroll 4
-            for (int k = 0; k < D; k += 4) {
-                float a2[2], b2[2];
-#pragma unroll
-                for (int i = 0; i < 2; ++i) a2[i] = K1s[(32 * wm + 16 * i + lr) * PD + k + lq];
-#pragma unroll
-                for (int j = 0; j < 2; ++j) b2[j] = Wt[(k + lq) * PD + 32 * wn + 16 * j + lr];
+                for (int u = 0; u < 4; ++u) *(floatx4*)(Wt + brow * PD + 16 * u + 4 * bsub) = tv[u];
+                __syncthreads();                               // T strip staged
+                floatx4 tn[4], pn[2][2];
+                if (s + 1 < SPQ) load_strip(s + 1, tn, pn);    // next strip in flight during this one
+                floatx4 acc[2][2];
 #pragma unroll
                 for (int i = 0; i < 2; ++i)
 #pragma unroll
-                    for (int j = 0; j < 2; ++j) acc[i][j] = mma(a2[i], b2[j], acc[i][j]);
-            }
-            __syncthreads();                                   // strip reads done
+                    for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0, 0, 0, 0};
+#pragma unroll 4
+                for (int k = 0; k < D; k += 4) {
+                    float ta[2], kb[2];
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
+                    for (int ti = 0; ti < 2; ++ti) ta[ti] = Wt[(k + lq) * PD + 32 * wm + 16 * ti + lr];
 #pragma unroll
-                for (int j = 0; j < 2; ++j)
+                    for (int tj = 0; tj < 2; ++tj) kb[tj] = K1s[(32 * wn + 16 * tj + lr) * PD + k + lq];
 #pragma unroll
-                    for (int v = 0; v < 4; ++v)
-                        Wt[(32 * wm + 16 * i + 4 * lq + v) * PD + 32 * wn + 16 * j + lr] = acc[i][j][v];
-            __syncthreads();
+                    for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const floatx4 k1t = *(const floatx4*)(Wt + brow * PD + 16 * u + 4 * bsub);
-                floatx4 d4 = floatx4{0, 0, 0, 0};
-                if (dv) d4 = *(const floatx4*)(dv + c0 + blane + 16 * u);
+                        for (int tj = 0; tj < 2; ++tj) acc[ti][tj] = mma(ta[ti], kb[tj], acc[ti][tj]);
+                }
 #pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    const float pn = ph[4 * u + c];
-                    const float q = k1t[c] + (s2 + d4[c]) * pn;
-                    qh[s][4 * u + c] = q;
-                    dot += (double)pn * (double)q;
+                for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+                    for (int tj = 0; tj < 2; ++tj) {
+                        const floatx4 d4 = ldn(rsD, olane + 16 * ti, c0 + 16 * SL * tj);
+                        floatx4 q;
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            const float pe = pb[ti][tj][v];
+                            q[v] = acc[ti][tj][v] + (s2 + d4[v]) * pe;
+                            dot += (double)pe * (double)q[v];
+                        }
+                        qh[s][ti][tj] = q;
+                    }
+                if (s + 1 < SPQ) {
+                    __syncthreads();                           // strip reads done before the next staging
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) tv[u] = tn[u];
+#pragma unroll
+                    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+                        for (int tj = 0; tj < 2; ++tj) pb[ti][tj] = pn[ti][tj];
                 }
             }
-            __syncthreads();                                   // staged q read out before the next strip
         }
+        // r for phase C, in flight across the barrier (phase B stored nothing)
+#pragma unroll
+        for (int s = 0; s < SPQ; ++s)
+#pragma unroll
+            for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+                for (int tj = 0; tj < 2; ++tj)
+                    rh[s][ti][tj] = ldc(rsR, olane + 16 * ti, (u0 + s) * D + 16 * SL * tj);
         target += a.bpr;
         if (!group_sum(dot, slotsB, a.bpr, rank, ctr, target, a.err, red, &s_tot, &s_ok)) return;
         if (tid == 0) {
@@ -352,19 +402,21 @@ __global__ __launch_bounds__(kFT) void k_fused_cg(FusedCgArgs a) {
         const float af = (float)fs.alpha;
         double rr2 = 0.0;
 #pragma unroll
-        for (int s = 0; s < SPQ; ++s) {
-            const int c0 = (u0 + s) * D;
+        for (int s = 0; s < SPQ; ++s)
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                floatx4 rv = ldc(rsR, blane + 16 * u, c0);
+            for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    rv[c] = __builtin_fmaf(-af, qh[s][4 * u + c], rv[c]);
-                    rr2 += (double)rv[c] * (double)rv[c];
+                for (int tj = 0; tj < 2; ++tj) {
+                    floatx4 r4 = rh[s][ti][tj];
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        r4[v] = __builtin_fmaf(-af, qh[s][ti][tj][v], r4[v]);
+                        rr2 += (double)r4[v] * (double)r4[v];
+                    }
+                    stc(rsR, olane + 16 * ti, (u0 + s) * D + 16 * SL * tj, r4);
                 }
-                stc(rsR, blane + 16 * u, c0, rv);
-            }
-        }
+        fence_stores();                                        // r visible to the group
+        load_p(u0);                                            // the next phase A's own data, early
         target += a.bpr;
         if (!group_sum(rr2, slotsC, a.bpr, rank, ctr, target, a.err, red, &s_tot, &s_ok)) return;
         if (tid == 0) {
@@ -403,10 +455,10 @@ __global__ __launch_bounds__(kFT) void k_fused_cg(FusedCgArgs a) {
             for (int u = 0; u < 4; ++u) {
                 const int sb = (u0 + s) * SL;
                 const floatx4 p4 = ldc(rsP, alane + 16 * u, sb);
-                floatx4 x4 = *(const floatx4*)(X + sb + alane + 16 * u);
+                floatx4 x4 = ldn(rsX, alane + 16 * u, sb);
 #pragma unroll
                 for (int c = 0; c < 4; ++c) x4[c] = __builtin_fmaf(af, p4[c], x4[c]);
-                *(floatx4*)(X + sb + alane + 16 * u) = x4;
+                stn(rsX, alane + 16 * u, sb, x4);
             }
     }
     if (rank == 0 && tid == 0) {
