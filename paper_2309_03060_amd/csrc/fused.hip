@@ -22,8 +22,11 @@
 // 40 against 56 for the separate kernels.  Data crossing blocks (p, T, r, the partial sums) is
 // written and read with agent-coherent accesses (the cache-policy bit that
 // the memory model uses for agent-scope atomics), so a barrier needs no cache
-// write-back.  The sums of a group are formed in rank order by every block of
-// the group, so all of them take the same decisions without another barrier.
+// write-back.  Barriers are split: a block arrives once its shared stores are
+// fenced and loads its own next operands (r for phase C, p for the next phase
+// A) until the group has arrived.  The sums of a group are formed in one fixed
+// order by every block of the group, so all of them take the same decisions
+// without another barrier.
 #include "fused.h"
 
 #include <algorithm>
@@ -79,16 +82,26 @@ __device__ inline double block_sum16(double v, double* red) {
 
 // This wave's memory operations have completed (stores included): issued by
 // every wave that stored data other blocks read after the next barrier.
-__device__ inline void fence_stores() { __builtin_amdgcn_s_waitcnt(0); }
+// The signal fences keep the compiler from moving memory operations across the wait.
+__device__ inline void fence_stores() {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
 
-// Group barrier: thread 0 arrives once the whole block is here, then waits for
-// the other blocks of the group.  Loads in flight stay in flight (a block
-// barrier waits for LDS operations only).  Returns false in every thread of the
-// block after a time-out (the flag is set; the launch is then void).
-__device__ inline bool group_wait(uint32_t* ctr, uint32_t target, uint32_t* err, int* s_ok) {
+// Split-phase group barrier.  group_arrive: once the whole block is here,
+// thread 0 counts the block in (every wave has fenced the stores the group
+// reads).  group_wait: thread 0 waits until the whole group has arrived; work
+// between the two calls touches only this block's own data and so overlaps
+// the wait.  A block barrier waits for LDS operations only, so loads stay in
+// flight across both.  group_wait returns false in every thread after a
+// time-out (the flag is set; the launch is then void).
+__device__ inline void group_arrive(uint32_t* ctr) {
     __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline bool group_wait(uint32_t* ctr, uint32_t target, uint32_t* err, int* s_ok) {
     if (threadIdx.x == 0) {
-        __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         int ok = 1;
         uint32_t spins = 0;
         while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
@@ -105,23 +118,22 @@ __device__ inline bool group_wait(uint32_t* ctr, uint32_t target, uint32_t* err,
     return *s_ok != 0;
 }
 
-// Group-wide sum of one value per thread: block sum, publish, barrier, then the
-// group's partials in rank order (the same total in every block).
-__device__ inline bool group_sum(double v, double* slots, int bpr, int rank, uint32_t* ctr, uint32_t target,
-                                 uint32_t* err, double* red, double* s_tot, int* s_ok) {
+// Publish this block's part of a group-wide sum (valid in every thread):
+// thread 0 stores it to the block's slot.  The caller fences the store.
+__device__ inline void group_publish(double v, double* slots, int rank, double* red) {
     const double part = block_sum16(v, red);
-    if (threadIdx.x == 0) {
-        store_coherent(slots + rank, part);
-        fence_stores();
-    }
-    if (!group_wait(ctr, target, err, s_ok)) return false;
-    if (threadIdx.x == 0) {
-        double t = 0.0;
-        for (int k = 0; k < bpr; ++k) t += load_coherent(slots + k);
-        *s_tot = t;
+    if (threadIdx.x == 0) store_coherent(slots + rank, part);
+}
+
+// After the barrier: the group's parts, one per lane of wave 0, summed in a
+// fixed butterfly order, so every block of the group gets the same total.
+__device__ inline void group_collect(const double* slots, int bpr, double* s_tot) {
+    if (threadIdx.x < 64) {
+        double v = threadIdx.x < bpr ? load_coherent(slots + threadIdx.x) : 0.0;
+        v = wave_sum(v);
+        if (threadIdx.x == 0) *s_tot = v;
     }
     __syncthreads();
-    return true;
 }
 
 // CG scalars of the group's right-hand side, kept in LDS and updated by
@@ -303,6 +315,7 @@ __global__ __launch_bounds__(kFT) void k_fused_cg(FusedCgArgs a) {
         }
         if (tid == 0) fs.pending = 0;
         fence_stores();                                        // p and T visible to the group
+        group_arrive(ctr);
         target += a.bpr;
         if (!group_wait(ctr, target, a.err, &s_ok)) return;
 
@@ -374,7 +387,10 @@ __global__ __launch_bounds__(kFT) void k_fused_cg(FusedCgArgs a) {
                 }
             }
         }
-        // r for phase C, in flight across the barrier (phase B stored nothing)
+        group_publish(dot, slotsB, rank, red);
+        if (tid < 64) fence_stores();                          // the part (phase B stored nothing else)
+        group_arrive(ctr);
+        // r for phase C, in flight across the barrier
 #pragma unroll
         for (int s = 0; s < SPQ; ++s)
 #pragma unroll
@@ -383,7 +399,8 @@ __global__ __launch_bounds__(kFT) void k_fused_cg(FusedCgArgs a) {
                 for (int tj = 0; tj < 2; ++tj)
                     rh[s][ti][tj] = ldc(rsR, olane + 16 * ti, (u0 + s) * D + 16 * SL * tj);
         target += a.bpr;
-        if (!group_sum(dot, slotsB, a.bpr, rank, ctr, target, a.err, red, &s_tot, &s_ok)) return;
+        if (!group_wait(ctr, target, a.err, &s_ok)) return;
+        group_collect(slotsB, a.bpr, &s_tot);
         if (tid == 0) {
             const double pq = s_tot;
             if (!(pq > 0.0) || !finite_d(pq)) {
@@ -415,10 +432,13 @@ __global__ __launch_bounds__(kFT) void k_fused_cg(FusedCgArgs a) {
                     }
                     stc(rsR, olane + 16 * ti, (u0 + s) * D + 16 * SL * tj, r4);
                 }
-        fence_stores();                                        // r visible to the group
+        group_publish(rr2, slotsC, rank, red);
+        fence_stores();                                        // r and the part visible to the group
+        group_arrive(ctr);
         load_p(u0);                                            // the next phase A's own data, early
         target += a.bpr;
-        if (!group_sum(rr2, slotsC, a.bpr, rank, ctr, target, a.err, red, &s_tot, &s_ok)) return;
+        if (!group_wait(ctr, target, a.err, &s_ok)) return;
+        group_collect(slotsC, a.bpr, &s_tot);
         if (tid == 0) {
             // convergence, iteration limit and reliable-update request
             const double tot = s_tot;
