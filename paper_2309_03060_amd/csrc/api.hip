@@ -438,25 +438,22 @@ int32_t capture_chunk(cola_op_s* op, const SysInfo& s, int prec, int nrhs, T* x,
     return COLA_OK;
 }
 
-// Fused-CG workspace: group sums, barrier counters and the time-out flag
+// Fused-CG workspace: barrier slots (which carry the group sums) and the time-out flag
 // (allocated on the first fused solve; sized for every co-resident block).
 int32_t ensure_fused(cola_op_s* op) {
     if (op->fused_max_blocks < 0) op->fused_max_blocks = fused_cg_max_blocks();
     if (op->fused_max_blocks < 8) return COLA_ERR_UNSUPPORTED;
-    if (op->fused_bar) return COLA_OK;
-    const int mb = op->fused_max_blocks;
-    const size_t bar_bytes = sizeof(uint32_t) * ((size_t)mb * kFusedBarStride + 1);
-    int32_t rc = alloc_bytes((void**)&op->fused_partials, sizeof(double) * 2 * (size_t)mb);
-    if (rc == COLA_OK) rc = alloc_bytes((void**)&op->fused_bar, bar_bytes);
+    if (op->fused_slots) return COLA_OK;
+    // three barrier-slot sets per block, then the time-out flag
+    const size_t bytes = sizeof(double) * 3 * (size_t)op->fused_max_blocks + sizeof(uint32_t);
+    int32_t rc = alloc_bytes((void**)&op->fused_slots, bytes);
     for (int b = 0; b < 2 && rc == COLA_OK; ++b)
         if (hipEventCreateWithFlags(&op->fused_done[b], hipEventDisableTiming) != hipSuccess) rc = COLA_ERR_HIP;
-    if (rc == COLA_OK && hipMemset(op->fused_bar, 0, bar_bytes) != hipSuccess) rc = COLA_ERR_HIP;
+    if (rc == COLA_OK && hipMemset(op->fused_slots, 0, bytes) != hipSuccess) rc = COLA_ERR_HIP;
     if (rc != COLA_OK) {               // leave the path off rather than half set up
         (void)hipGetLastError();
-        if (op->fused_partials) (void)hipFree(op->fused_partials);
-        if (op->fused_bar) (void)hipFree(op->fused_bar);
-        op->fused_partials = nullptr;
-        op->fused_bar = nullptr;
+        if (op->fused_slots) (void)hipFree(op->fused_slots);
+        op->fused_slots = nullptr;
         op->fused_max_blocks = 0;
     }
     return rc;
@@ -487,9 +484,8 @@ int32_t run_cg_fused(cola_op_s* op, const SysInfo& s, int nrhs, float* x, float*
     a.K3 = op->fac32 + s.fac_off[2];
     a.dvec = s.diag_off >= 0 ? op->diag32 + s.diag_off : nullptr;
     a.sigma2 = s.sigma2;
-    a.partials = op->fused_partials;
-    a.bar = op->fused_bar;
-    a.err = op->fused_bar + (size_t)op->fused_max_blocks * kFusedBarStride;
+    a.slots = op->fused_slots;
+    a.err = (uint32_t*)(op->fused_slots + 3 * (size_t)op->fused_max_blocks);
     a.cnt = w.cnt;
     float* t = (float*)w.inter[0];
     int last = -1;
@@ -501,7 +497,7 @@ int32_t run_cg_fused(cola_op_s* op, const SysInfo& s, int nrhs, float* x, float*
             a.p = p + g0 * n;
             a.T = t + g0 * n;
             a.cg = w.cg + g0;
-            HIP_TRY(fill_i32((int32_t*)op->fused_bar, 0, (int64_t)a.nrhs * kFusedBarStride, st));
+            HIP_TRY(fill_i32((int32_t*)op->fused_slots, -1, (int64_t)a.nrhs * bpr * 3 * 2, st));   // all bits set
             ProfScope ps(op->prof, "cg_fused", st);
             const hipError_t le = launch_fused_cg(a, st);
             if (le != hipSuccess) {
@@ -1105,7 +1101,7 @@ int32_t cola_op_destroy(cola_op_t op) {
     for (hipEvent_t e : op->fused_done)
         if (e) (void)hipEventDestroy(e);
     void* ptrs[] = {op->fac64, op->fac32, op->facbf, op->diag64, op->diag32, op->grad_buf, op->eig_lam,
-                    op->eig_tmp, op->fused_partials, op->fused_bar};
+                    op->eig_tmp, op->fused_slots};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     delete op;

@@ -5,8 +5,6 @@
 
 namespace cola {
 
-constexpr int kFusedBarStride = 64;    // barrier counters 256 bytes apart (one cache line each)
-
 // One launch runs up to `iters` CG iterations for `nrhs` right-hand sides of
 // one system K1 (x) K2 (x) K3 + diag(d) + sigma2 I with n = 64^3.  Every
 // right-hand side is owned by a group of `bpr` co-resident blocks that meet at
@@ -22,8 +20,7 @@ struct FusedCgArgs {
     float* x; float* r; float* p;   // right-hand side g at offset g * n
     float* T;            // intermediate (K2, K3 product), same layout
     CgState* cg;         // right-hand side g at cg[g]
-    double* partials;    // 2 * nrhs * bpr
-    uint32_t* bar;       // nrhs counters, kFusedBarStride apart, zero at launch
+    double* slots;       // 3 * nrhs * bpr barrier slots, all bits set at launch
     uint32_t* err;       // set to 1 when a barrier wait times out
     SolveCounters* cnt;
 };

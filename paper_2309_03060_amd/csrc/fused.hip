@@ -22,11 +22,12 @@
 // 40 against 56 for the separate kernels.  Data crossing blocks (p, T, r, the partial sums) is
 // written and read with agent-coherent accesses (the cache-policy bit that
 // the memory model uses for agent-scope atomics), so a barrier needs no cache
-// write-back.  Barriers are split: a block arrives once its shared stores are
-// fenced and loads its own next operands (r for phase C, p for the next phase
-// A) until the group has arrived.  The sums of a group are formed in one fixed
-// order by every block of the group, so all of them take the same decisions
-// without another barrier.
+// write-back.  Each group barrier carries the block's part of the next group
+// sum: a block posts its part once its shared stores are fenced, loads its own
+// next operands (r for phase C, p for the next phase A), then polls the
+// group's posts, which both waits and gathers.  The sums of a group are formed
+// in one fixed order by every block of the group, so all of them take the
+// same decisions without another barrier.
 #include "fused.h"
 
 #include <algorithm>
@@ -89,51 +90,57 @@ __device__ inline void fence_stores() {
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
-// Split-phase group barrier.  group_arrive: once the whole block is here,
-// thread 0 counts the block in (every wave has fenced the stores the group
-// reads).  group_wait: thread 0 waits until the whole group has arrived; work
-// between the two calls touches only this block's own data and so overlaps
-// the wait.  A block barrier waits for LDS operations only, so loads stay in
-// flight across both.  group_wait returns false in every thread after a
-// time-out (the flag is set; the launch is then void).
-__device__ inline void group_arrive(uint32_t* ctr) {
+// Group barrier that carries one value per block.  Each group owns three
+// sets of bpr slots, cycled by the barrier count k.  A slot holds a sentinel
+// until its block posts a value; a block has arrived once its slot in set
+// k mod 3 is not the sentinel, so polling the slots both waits and gathers
+// the values (no counter, no second round trip).  After barrier k a block
+// resets its own slot in set (k + 2) mod 3: every block read that set before
+// arriving at barrier k, and the reset is fenced before the block's next post,
+// so no block can see it stale at barrier k + 2.
+constexpr uint64_t kSlotEmpty = ~0ull;                 // a NaN pattern arithmetic never makes
+
+// Post this block's value (the caller's waves have fenced every store the
+// group reads after the barrier).
+__device__ inline void group_post(double v, double* gslots, int bpr, int rank, uint32_t k) {
     __syncthreads();
-    if (threadIdx.x == 0) __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ inline bool group_wait(uint32_t* ctr, uint32_t target, uint32_t* err, int* s_ok) {
     if (threadIdx.x == 0) {
+        const double c = (v == v) ? v : __builtin_bit_cast(double, 0x7ff8000000000000ull);   // one NaN
+        store_coherent(gslots + (k % 3) * bpr + rank, c);
+    }
+}
+
+// Wait for the group and sum the posted values in a fixed butterfly order
+// (the same total in every block).  Loads issued since the post stay in
+// flight.  Returns false in every thread after a time-out (the flag is set;
+// the launch is then void).
+__device__ inline bool group_gather(double* gslots, int bpr, int rank, uint32_t k, uint32_t* err, double* s_tot,
+                                    int* s_ok) {
+    if (threadIdx.x < 64) {
+        const int lane = threadIdx.x;
+        const double* set = gslots + (k % 3) * bpr;
+        double v = 0.0;
         int ok = 1;
-        uint32_t spins = 0;
-        while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-            if (++spins > kSpinLimit) {
-                __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        for (uint32_t spins = 0;; ++spins) {
+            v = lane < bpr ? load_coherent(set + lane) : 0.0;
+            const bool ready = lane >= bpr || __builtin_bit_cast(uint64_t, v) != kSlotEmpty;
+            if (__all(ready)) break;
+            if (spins > kSpinLimit) {
+                if (lane == 0) __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 ok = 0;
                 break;
             }
             __builtin_amdgcn_s_sleep(1);
         }
-        *s_ok = ok;
+        v = wave_sum(v);
+        if (lane == 0) {
+            *s_tot = v;
+            *s_ok = ok;
+            store_coherent(gslots + ((k + 2) % 3) * bpr + rank, __builtin_bit_cast(double, kSlotEmpty));
+        }
     }
     __syncthreads();
     return *s_ok != 0;
-}
-
-// Publish this block's part of a group-wide sum (valid in every thread):
-// thread 0 stores it to the block's slot.  The caller fences the store.
-__device__ inline void group_publish(double v, double* slots, int rank, double* red) {
-    const double part = block_sum16(v, red);
-    if (threadIdx.x == 0) store_coherent(slots + rank, part);
-}
-
-// After the barrier: the group's parts, one per lane of wave 0, summed in a
-// fixed butterfly order, so every block of the group gets the same total.
-__device__ inline void group_collect(const double* slots, int bpr, double* s_tot) {
-    if (threadIdx.x < 64) {
-        double v = threadIdx.x < bpr ? load_coherent(slots + threadIdx.x) : 0.0;
-        v = wave_sum(v);
-        if (threadIdx.x == 0) *s_tot = v;
-    }
-    __syncthreads();
 }
 
 // CG scalars of the group's right-hand side, kept in LDS and updated by
@@ -183,10 +190,8 @@ __global__ __launch_bounds__(kFT) void k_fused_cg(FusedCgArgs a) {
     const auto rsP = vec_rsrc(a.p + (int64_t)grp * NV);
     const auto rsT = vec_rsrc(a.T + (int64_t)grp * NV);
     const float s2 = (float)a.sigma2;
-    double* slotsB = a.partials + (int64_t)grp * a.bpr;
-    double* slotsC = a.partials + (int64_t)(a.nrhs + grp) * a.bpr;
-    uint32_t* ctr = a.bar + (int64_t)grp * kFusedBarStride;
-    uint32_t target = 0;
+    double* gslots = a.slots + (int64_t)grp * 3 * a.bpr;
+    uint32_t k = 0;                                  // barriers passed in this launch
 
     for (int e = tid; e < D * D; e += kFT) {
         const int rr = e / D, c = e % D;
@@ -315,9 +320,8 @@ __global__ __launch_bounds__(kFT) void k_fused_cg(FusedCgArgs a) {
         }
         if (tid == 0) fs.pending = 0;
         fence_stores();                                        // p and T visible to the group
-        group_arrive(ctr);
-        target += a.bpr;
-        if (!group_wait(ctr, target, a.err, &s_ok)) return;
+        group_post(0.0, gslots, a.bpr, rank, k);
+        if (!group_gather(gslots, a.bpr, rank, k++, a.err, &s_tot, &s_ok)) return;
 
         // ---------------- phase B ----------------
         // q = K1 T + (sigma2 + d) p per strip, computed transposed so each lane holds
@@ -387,9 +391,9 @@ __global__ __launch_bounds__(kFT) void k_fused_cg(FusedCgArgs a) {
                 }
             }
         }
-        group_publish(dot, slotsB, rank, red);
-        if (tid < 64) fence_stores();                          // the part (phase B stored nothing else)
-        group_arrive(ctr);
+        const double dot_blk = block_sum16(dot, red);
+        if (tid < 64) fence_stores();                          // the last slot reset (phase B stored nothing)
+        group_post(dot_blk, gslots, a.bpr, rank, k);
         // r for phase C, in flight across the barrier
 #pragma unroll
         for (int s = 0; s < SPQ; ++s)
@@ -398,9 +402,7 @@ __global__ __launch_bounds__(kFT) void k_fused_cg(FusedCgArgs a) {
 #pragma unroll
                 for (int tj = 0; tj < 2; ++tj)
                     rh[s][ti][tj] = ldc(rsR, olane + 16 * ti, (u0 + s) * D + 16 * SL * tj);
-        target += a.bpr;
-        if (!group_wait(ctr, target, a.err, &s_ok)) return;
-        group_collect(slotsB, a.bpr, &s_tot);
+        if (!group_gather(gslots, a.bpr, rank, k++, a.err, &s_tot, &s_ok)) return;
         if (tid == 0) {
             const double pq = s_tot;
             if (!(pq > 0.0) || !finite_d(pq)) {
@@ -432,13 +434,11 @@ __global__ __launch_bounds__(kFT) void k_fused_cg(FusedCgArgs a) {
                     }
                     stc(rsR, olane + 16 * ti, (u0 + s) * D + 16 * SL * tj, r4);
                 }
-        group_publish(rr2, slotsC, rank, red);
-        fence_stores();                                        // r and the part visible to the group
-        group_arrive(ctr);
+        const double rr_blk = block_sum16(rr2, red);
+        fence_stores();                                        // r visible to the group
+        group_post(rr_blk, gslots, a.bpr, rank, k);
         load_p(u0);                                            // the next phase A's own data, early
-        target += a.bpr;
-        if (!group_wait(ctr, target, a.err, &s_ok)) return;
-        group_collect(slotsC, a.bpr, &s_tot);
+        if (!group_gather(gslots, a.bpr, rank, k++, a.err, &s_tot, &s_ok)) return;
         if (tid == 0) {
             // convergence, iteration limit and reliable-update request
             const double tot = s_tot;

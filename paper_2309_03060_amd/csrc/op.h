@@ -124,8 +124,7 @@ struct cola_op_s {
     bool use_gemm3 = true;          // FP32 one-term three-mode operators with 256-wide modes: dense-GEMM MVM
     bool use_fused = true;          // FP32 one-term three-mode operators with 64-wide modes: persistent fused CG
     int fused_max_blocks = -1;      // co-resident fused-CG blocks (-1: not yet queried)
-    double* fused_partials = nullptr;   // fused-CG group sums (2 * fused_max_blocks)
-    uint32_t* fused_bar = nullptr;      // fused-CG barrier counters, then the time-out flag
+    double* fused_slots = nullptr;      // fused-CG barrier slots (3 * fused_max_blocks), then the time-out flag
     hipEvent_t fused_done[2] = {nullptr, nullptr};
     bool resident_ok = false;       // every system fits the resident batched kernel
     bool use_resident = true;
