@@ -18,6 +18,9 @@ grad     solve VJP (App. B.2, autograd rule 1) by three routes: dense
          -lambda x^T contraction, closed-form factor contractions, finite
          differences
 lowprec  bf16 / fp32 rounding emulator (diagnostic; App. C.3 context)
+slq      log det by stochastic Lanczos quadrature with the tridiagonal taken
+         from CG coefficients, Kronecker closed forms of log det and
+         Tr(A^{-1}) (App. A "Derived functions"; App. C base-case table)
 
 Conventions: vec is row-major (C order), so (K1 (x) K2) x = vec(K1 X K2^T)
 with X = x.reshape(n1, n2), matching numpy.kron and the row-major form of the
