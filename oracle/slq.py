@@ -34,17 +34,12 @@ TEST INFRASTRUCTURE: see the package docstring.
 """
 from __future__ import annotations
 
-from typing import Callable, List, Tuple
+from typing import Callable, Tuple
 
 import numpy as np
 import scipy.linalg
 
 from . import direct
-
-
-def rademacher(rng: np.random.Generator, count: int, n: int) -> np.ndarray:
-    """count probe vectors of length n with independent +-1 entries."""
-    return np.where(rng.random((count, n)) < 0.5, -1.0, 1.0)
 
 
 def lanczos(apply_A: Callable[[np.ndarray], np.ndarray], b: np.ndarray, m: int) -> Tuple[np.ndarray, np.ndarray]:
@@ -121,6 +116,9 @@ def probe_logdets(apply_A: Callable[[np.ndarray], np.ndarray], Z: np.ndarray, m:
     """Per-probe estimates ||z||^2 e1^T log(T) e1 with T from the CG coefficients."""
     out = []
     for z in np.asarray(Z, dtype=np.float64):
+        if not np.any(z):                 # z = 0: z^T log(A) z = 0 (no iteration runs)
+            out.append(0.0)
+            continue
         a, b = cg_coefficients(apply_A, z, m, tol)
         d, e = tridiagonal_from_cg(a, b)
         out.append(float(z @ z) * quadrature(d, e, np.log))

@@ -12,6 +12,7 @@
 """
 import numpy as np
 
+import workloads as wl
 from oracle import kron, slq
 
 
@@ -68,7 +69,7 @@ def test_slq_mean_within_statistical_error():
     facs = [_spd(rng, k, 0.3) for k in (6, 5, 4)]
     sigma2 = 0.5
     terms = [facs]
-    Z = slq.rademacher(rng, 1500, 120)
+    Z = wl.rademacher_probes(rng, 1500, 120)
     est = slq.probe_logdets(_mvm(terms, sigma2), Z, 30)
     exact = slq.kron_logdet(facs, sigma2)
     err = abs(est.mean() - exact)
@@ -91,7 +92,7 @@ def test_probe_gradient_of_logdet_wrt_factor():
     # exact: dlogdet/dK1[a, b] = Tr(A^{-1} (E_ab (x) K2)) = sum_{i, j} Ainv[(b, i), (a, j)] K2[i, j]
     Ai = Ainv.reshape(n1, n2, n1, n2)
     exact = np.einsum("bian,in->ab", Ai, facs[1])
-    Z = slq.rademacher(rng, 4000, n1 * n2)
+    Z = wl.rademacher_probes(rng, 4000, n1 * n2)
     L = Z @ Ainv                                   # rows: A^{-1} z (A symmetric)
     # (A^{-1} z)^T (E_ab (x) K2) z = sum_{i, j} L[a, i] K2[i, j] Z[b, j]  per probe
     Lr, Zr = L.reshape(-1, n1, n2), Z.reshape(-1, n1, n2)

@@ -181,6 +181,11 @@ def config5(m: int = 1024, nterms: int = 4, nrhs: int = 16, seed: int = 5) -> Wo
                     description=f"sum_{nterms} U(x)V + diag(d), {m}^2, {nrhs} RHS")
 
 
+def rademacher_probes(rng: np.random.Generator, count: int, n: int) -> np.ndarray:
+    """count probe vectors of length n with independent +-1 entries (E[z z^T] = I)."""
+    return np.where(rng.random((count, n)) < 0.5, -1.0, 1.0)
+
+
 def random_system(rng: np.random.Generator, dims, nterms: int = 1, diag: bool = False,
                   sigma2: float = 0.1, kind: str = "wishart") -> System:
     """Small generic SPD system for parity sweeps (tiles, ragged tails, edge cases).
