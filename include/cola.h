@@ -172,6 +172,31 @@ int32_t cola_cg_solve_backward(cola_op_t op, const double* X, const double* G, i
                                void* const* dfactors, void* const* ddiag, double* dsigma2,
                                cola_solve_info* info, void* stream);
 
+/* Stochastic Lanczos quadrature estimate of log det A per system.  log det A
+ * = Tr(Log(A)) for a symmetric positive definite A (App. A, derived
+ * functions); stochastic Lanczos quadrature is the base-case iterative method
+ * for such functions (App. C, table of base-case iterative algorithms).
+ * Z: nprobes probe vectors per system (packed FP64 like B of cola_cg_solve,
+ * device), e.g. Rademacher (+-1) entries, so that E[z z^T] = I.  One FP64 CG
+ * over all probes (x0 = 0, at most max_iters iterations, stopping per probe
+ * at ||r|| <= tol ||z||) records its step lengths and residual ratios; they
+ * give each probe's Lanczos tridiagonal T (CG-Lanczos relation), and the
+ * device forms est = ||z||^2 e1^T log(T) e1 by Gauss quadrature and
+ * logdet = mean of est.
+ *   X:      NULL, or device FP64 (packed like Z) receiving A^{-1} Z (the
+ *           Hutchinson estimate of d log det / d theta is mean_z
+ *           (A^{-1} z)^T (dA/dtheta) z: cola_cg_solve_backward with X = G = Z
+ *           returns it times -nprobes);
+ *   logdet: device array of nsys doubles;
+ *   est:    NULL, or device array of nsys * nprobes per-probe estimates (NaN
+ *           for a probe whose CG broke down);
+ *   info:   NULL, or the per-probe CG outcome as for cola_cg_solve.
+ * 1 <= max_iters <= 2048.  Enqueued on `stream`; the host waits on it every
+ * 32 iterations to stop early.  The first call for a given nprobes and
+ * max_iters allocates workspace. */
+int32_t cola_slq_logdet(cola_op_t op, const double* Z, int32_t nprobes, double tol, int32_t max_iters,
+                        double* X, double* logdet, double* est, cola_solve_info* info, void* stream);
+
 /* Direct solve X = A^{-1} B of single-term systems A = K_1 (x) .. (x) K_F +
  * sigma2 * I by the Kronecker eigenvalue rules (App. A: the eigenvectors of a
  * Kronecker product are the Kronecker products of the factors' eigenvectors

@@ -39,7 +39,7 @@ PREC_BY_NAME = {"fp64": COLA_PREC_FP64, "fp32": COLA_PREC_FP32,
                 "bf16": COLA_PREC_BF16, "bf16x3": COLA_PREC_BF16X3}
 
 EXPORTED = ("cola_op_create", "cola_op_destroy", "cola_op_size", "cola_kron_matvec",
-            "cola_cg_solve", "cola_cg_solve_backward", "cola_eig_solve", "cola_autotune",
+            "cola_cg_solve", "cola_cg_solve_backward", "cola_eig_solve", "cola_slq_logdet", "cola_autotune",
             "cola_op_set_engine", "cola_profile_enable", "cola_profile_read", "cola_status_string")
 
 
@@ -86,6 +86,7 @@ def lib():
         L.cola_cg_solve_backward.argtypes = [vp, vp, vp, i32, ctypes.POINTER(SolveOpts), vp,
                                              ctypes.POINTER(vp), ctypes.POINTER(vp), vp, vp, vp]
         L.cola_eig_solve.argtypes = [vp, vp, vp, i32, vp]
+        L.cola_slq_logdet.argtypes = [vp, vp, i32, dbl, i32, vp, vp, vp, vp, vp]
         L.cola_autotune.argtypes = [vp, i32, vp]
         L.cola_op_set_engine.argtypes = [vp, i32, i32]
         L.cola_profile_enable.argtypes = [vp, i32]

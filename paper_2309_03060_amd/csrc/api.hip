@@ -18,6 +18,7 @@
 #include "op.h"
 #include "resident.h"
 #include "slab.h"
+#include "slq.h"
 #include "vector.h"
 
 using namespace cola;
@@ -354,7 +355,8 @@ int32_t enqueue_iteration(cola_op_s* op, const SysInfo& s, int prec, int nrhs, T
     int32_t rc = enqueue_mvm(op, s, prec, nrhs, p, r, q, a, st);
     if (rc != COLA_OK) return rc;
     ProfScope ps(op->prof, sizeof(T) == 8 ? "update_fp64" : "update", st);
-    HIP_TRY(cg_update<T>(x, r, p, q, s.n, nrhs, w.cg, w.partials, (int)w.part_stride, w.counters, w.cnt, st));
+    HIP_TRY(cg_update<T>(x, r, p, q, s.n, nrhs, w.cg, w.partials, (int)w.part_stride, w.counters, w.cnt, st,
+                         sizeof(T) == 8 ? w.hist : nullptr, w.hist_len));
     return COLA_OK;
 }
 
@@ -570,7 +572,7 @@ int32_t run_cg(cola_op_s* op, const SysInfo& s, int prec, int nrhs, T* x, T* r, 
     GraphSet* gs = nullptr;
     if (op->graphs_ok) {
         GraphKey key{&s, prec, nrhs, x, r, p, q, chunk, (op->prof.enabled ? 1 : 0) + (tail ? 2 : 0),
-                     op->tiles_version};
+                     op->tiles_version, sizeof(T) == 8 ? w.hist : nullptr};
         auto it = op->graphs.find(key);
         if (it == op->graphs.end() && op->graphs.size() >= 32) destroy_graphs(op);   // keep the cache bounded
         if (it == op->graphs.end()) {
@@ -647,7 +649,7 @@ int32_t solve_system(cola_op_s* op, const SysInfo& s, const double* B, double* X
         int32_t rc = run_cg<double>(op, s, COLA_PREC_FP64, nrhs, x, r, p, q, o->max_iters, o->check_every, nullptr,
                                     st);
         if (rc != COLA_OK) return rc;
-        HIP_TRY(copy_f64(x, X, (int64_t)nrhs * n, st));
+        if (X) HIP_TRY(copy_f64(x, X, (int64_t)nrhs * n, st));
         if (info) HIP_TRY(write_info(info, nullptr, w.cg, nrhs, st));
         return COLA_OK;
     }
@@ -1101,7 +1103,7 @@ int32_t cola_op_destroy(cola_op_t op) {
     for (hipEvent_t e : op->fused_done)
         if (e) (void)hipEventDestroy(e);
     void* ptrs[] = {op->fac64, op->fac32, op->facbf, op->diag64, op->diag32, op->grad_buf, op->eig_lam,
-                    op->eig_tmp, op->fused_slots};
+                    op->eig_tmp, op->fused_slots, op->slq_buf};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     delete op;
@@ -1155,6 +1157,44 @@ int32_t cola_cg_solve(cola_op_t op, const double* B, double* X, int32_t nrhs, co
         const size_t off = (size_t)nrhs * s.vec_off;
         rc = solve_system(op, s, B + off, X + off, nrhs, opts, info ? info + i * nrhs : nullptr, st);
         if (rc != COLA_OK) return rc;
+    }
+    return COLA_OK;
+}
+
+int32_t cola_slq_logdet(cola_op_t op, const double* Z, int32_t nprobes, double tol, int32_t max_iters,
+                        double* X, double* logdet, double* est, cola_solve_info* info, void* stream) {
+    if (!op || !Z || !logdet || nprobes < 1 || !finite_pos(tol) || max_iters < 1) return COLA_ERR_INVALID_ARG;
+    if (slq_threads_per_block(max_iters) < 1) return COLA_ERR_INVALID_ARG;
+    hipStream_t st = S(stream);
+    int32_t rc = ensure_ws(op, nprobes, st);
+    if (rc != COLA_OK) return rc;
+    const size_t hist_elems = (size_t)nprobes * 2 * (size_t)max_iters;
+    const size_t need = hist_elems + (size_t)nprobes;              // history, then per-probe estimates
+    if (op->slq_elems < need) {
+        if (op->slq_buf) (void)hipFree(op->slq_buf);
+        op->slq_buf = nullptr;
+        op->slq_elems = 0;
+        rc = alloc_bytes((void**)&op->slq_buf, need * sizeof(double));
+        if (rc != COLA_OK) return rc;
+        op->slq_elems = need;
+    }
+    cola_solve_opts o{};
+    o.tol = tol;
+    o.max_iters = max_iters;
+    o.prec = COLA_PREC_FP64;
+    o.check_every = 32;
+    Workspace& w = op->ws;
+    for (size_t i = 0; i < op->sys.size(); ++i) {
+        const SysInfo& s = op->sys[i];
+        const size_t off = (size_t)nprobes * s.vec_off;
+        w.hist = op->slq_buf;
+        w.hist_len = max_iters;
+        rc = solve_system(op, s, Z + off, X ? X + off : nullptr, nprobes, &o, info ? info + i * nprobes : nullptr, st);
+        w.hist = nullptr;
+        w.hist_len = 0;
+        if (rc != COLA_OK) return rc;
+        double* e = est ? est + i * nprobes : op->slq_buf + hist_elems;
+        HIP_TRY(slq_logdet(op->slq_buf, max_iters, w.cg, nprobes, e, logdet + i, st));
     }
     return COLA_OK;
 }

@@ -41,6 +41,8 @@ struct Workspace {
     OuterState* outer = nullptr;
     SolveCounters* cnt = nullptr;
     int32_t* host_flag = nullptr;     // pinned
+    double* hist = nullptr;           // while set: (alpha, beta) of every FP64 CG iteration, hist_len per RHS
+    int hist_len = 0;
 };
 
 // Per-kernel-class timing with HIP events recorded around launches.  Direct
@@ -78,10 +80,10 @@ struct GraphSet {
 };
 struct GraphKey {
     const void* sys; int prec; int nrhs; const void* x; const void* r; const void* p; const void* q;
-    int chunk; int profiled; int tiles_version;
+    int chunk; int profiled; int tiles_version; const void* hist;
     bool operator<(const GraphKey& o) const {
-        return std::tie(sys, prec, nrhs, x, r, p, q, chunk, profiled, tiles_version) <
-               std::tie(o.sys, o.prec, o.nrhs, o.x, o.r, o.p, o.q, o.chunk, o.profiled, o.tiles_version);
+        return std::tie(sys, prec, nrhs, x, r, p, q, chunk, profiled, tiles_version, hist) <
+               std::tie(o.sys, o.prec, o.nrhs, o.x, o.r, o.p, o.q, o.chunk, o.profiled, o.tiles_version, o.hist);
     }
 };
 
@@ -124,6 +126,8 @@ struct cola_op_s {
     bool use_gemm3 = true;          // FP32 one-term three-mode operators with 256-wide modes: dense-GEMM MVM
     bool use_fused = true;          // FP32 one-term three-mode operators with 64-wide modes: persistent fused CG
     int fused_max_blocks = -1;      // co-resident fused-CG blocks (-1: not yet queried)
+    double* slq_buf = nullptr;      // SLQ: CG coefficient history and per-probe estimates
+    size_t slq_elems = 0;
     double* fused_slots = nullptr;      // fused-CG barrier slots (3 * fused_max_blocks), then the time-out flag
     hipEvent_t fused_done[2] = {nullptr, nullptr};
     bool resident_ok = false;       // every system fits the resident batched kernel

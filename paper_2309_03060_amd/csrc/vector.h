@@ -27,9 +27,12 @@ template <typename T>
 hipError_t reliable_apply(const double* r64, T* rlo, int64_t n, int nrhs, CgState* cg, double* partials,
                           int part_stride, uint32_t* counters, SolveCounters* cnt, hipStream_t s);
 
+// hist (or null): per right-hand side g, hist_len (alpha, beta) pairs; iteration
+// i (1-based) of g stores its step length and r.r ratio at pair i - 1.
 template <typename T>
 hipError_t cg_update(T* x, T* r, const T* p, const T* q, int64_t n, int nrhs, CgState* cg, double* partials,
-                     int part_stride, uint32_t* counters, SolveCounters* cnt, hipStream_t s);
+                     int part_stride, uint32_t* counters, SolveCounters* cnt, hipStream_t s,
+                     double* hist = nullptr, int hist_len = 0);
 
 template <typename T>
 hipError_t refine_accumulate(double* x64, const T* d, int64_t n, int nrhs, const OuterState* outer,

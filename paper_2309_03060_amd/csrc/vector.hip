@@ -147,7 +147,8 @@ __global__ __launch_bounds__(kThreads) void k_cg_prepare(const double* src, T* r
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_cg_update(T* x, T* r, const T* p, const T* q, int64_t n,
                                                         CgState* cg, double* partials, int part_stride,
-                                                        uint32_t* counters, SolveCounters* cnt) {
+                                                        uint32_t* counters, SolveCounters* cnt, double* hist,
+                                                        int hist_len) {
     __shared__ double red[4];
     const int64_t g = blockIdx.y;
     if (!cg[g].active) return;
@@ -186,6 +187,11 @@ __global__ __launch_bounds__(kThreads) void k_cg_update(T* x, T* r, const T* p, 
         threadIdx.x == 0) {
         CgState& st = cg[g];
         st.iters += 1;
+        if (hist && st.iters <= hist_len) {      // the CG coefficients behind the Lanczos tridiagonal
+            double* h = hist + ((int64_t)g * hist_len + st.iters - 1) * 2;
+            h[0] = st.alpha;
+            h[1] = tot / st.rho;
+        }
         bool stop = true;
         if (!finite_d(tot)) {
             st.status = COLA_ERR_NONFINITE;
@@ -409,16 +415,17 @@ template hipError_t reliable_apply<float>(const double*, float*, int64_t, int, C
 
 template <typename T>
 hipError_t cg_update(T* x, T* r, const T* p, const T* q, int64_t n, int nrhs, CgState* cg, double* partials,
-                     int part_stride, uint32_t* counters, SolveCounters* cnt, hipStream_t s) {
+                     int part_stride, uint32_t* counters, SolveCounters* cnt, hipStream_t s, double* hist,
+                     int hist_len) {
     dim3 grid(vec_blocks_per_rhs(n), nrhs);
     hipLaunchKernelGGL(k_cg_update<T>, grid, dim3(kThreads), 0, s, x, r, p, q, n, cg, partials, part_stride,
-                       counters, cnt);
+                       counters, cnt, hist, hist_len);
     return hipGetLastError();
 }
 template hipError_t cg_update<float>(float*, float*, const float*, const float*, int64_t, int, CgState*, double*,
-                                     int, uint32_t*, SolveCounters*, hipStream_t);
+                                     int, uint32_t*, SolveCounters*, hipStream_t, double*, int);
 template hipError_t cg_update<double>(double*, double*, const double*, const double*, int64_t, int, CgState*,
-                                      double*, int, uint32_t*, SolveCounters*, hipStream_t);
+                                      double*, int, uint32_t*, SolveCounters*, hipStream_t, double*, int);
 
 template <typename T>
 hipError_t refine_accumulate(double* x64, const T* d, int64_t n, int nrhs, const OuterState* outer,

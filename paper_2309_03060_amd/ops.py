@@ -194,6 +194,33 @@ class KronOperator:
                                                            _stream_ptr()))
         return X
 
+    def logdet(self, Z: torch.Tensor, nprobes: int, tol: float = 1e-8, max_iters: int = 200,
+               want_solution: bool = False):
+        """Stochastic Lanczos quadrature estimate of log det A per system (cola_slq_logdet).
+
+        Z: packed float64 probes (nprobes per system, e.g. +-1 entries).  Returns (logdet per
+        system, per-probe estimates, A^{-1} Z or None, info tensor)."""
+        if Z.dtype != torch.float64 or not Z.is_contiguous():
+            raise ValueError("Z must be a contiguous float64 device tensor")
+        nsys = len(self.systems)
+        ld = torch.empty(nsys, dtype=torch.float64, device=Z.device)
+        est = torch.empty(nsys * nprobes, dtype=torch.float64, device=Z.device)
+        X = torch.empty_like(Z) if want_solution else None
+        info = torch.empty(len(self.sizes) * nprobes * 6, dtype=torch.int32, device=Z.device)
+        L.check("cola_slq_logdet", self.lib.cola_slq_logdet(
+            self.handle, Z.data_ptr(), nprobes, tol, max_iters, X.data_ptr() if X is not None else None,
+            ld.data_ptr(), est.data_ptr(), info.data_ptr(), _stream_ptr()))
+        return ld, est, X, info
+
+    def logdet_grad(self, Z: torch.Tensor, nprobes: int, tol: float = 1e-8, max_iters: int = 10000):
+        """Hutchinson estimate of d log det A / d(factors, diagonal, sigma2): the mean over probes of
+        (A^{-1} z)^T (dA/dtheta) z, i.e. the adjoint backward with X = G = Z divided by -nprobes."""
+        _, dfac, ddiag, ds2, info = self.solve_backward(Z, Z, nprobes, tol=tol, max_iters=max_iters, prec="fp64")
+        scale = -1.0 / nprobes
+        dfac = [[[g * scale for g in row] for row in sysf] for sysf in dfac]
+        ddiag = [None if d is None else d * scale for d in ddiag]
+        return dfac, ddiag, ds2 * scale, info
+
     def autotune(self, nrhs: int):
         L.check("cola_autotune", self.lib.cola_autotune(self.handle, nrhs, _stream_ptr()))
 
