@@ -77,6 +77,11 @@ def parse():
     ap.add_argument("--trace-summary", nargs=3, default=None, metavar=("PREFIX", "CMD", "TITLE"),
                     help="summarise rocprofv3 kernel-trace CSVs PREFIX_kernel_stats.csv / _kernel_trace.csv")
     ap.add_argument("--pmc-out", default=None, help="with --pmc-summary: JSON file to merge the traffic record into")
+    ap.add_argument("--autograd", action="store_true",
+                    help="backward runtime and peak memory: adjoint rules against unrolled autodiff (JSON)")
+    ap.add_argument("--autograd-steps", type=int, nargs="+", default=[16, 32, 64, 128, 256, 512, 1024])
+    ap.add_argument("--autograd-sizes", type=int, nargs="+", default=[16, 24, 32, 48, 64, 96])
+    ap.add_argument("--autograd-logdet-steps", type=int, nargs="+", default=[16, 32, 64, 128, 256])
     ap.add_argument("--max-iters", type=int, default=None,
                     help="cap on CG iterations per solve (default: the workload's own limit)")
     return ap.parse_args()
@@ -130,6 +135,251 @@ def slq_measure(op, factors, sigma2, n, nprobes=32, max_iters=300, tol=1e-8, see
            "note": "FP64 CG over the probes to 1e-8 (at most 300 steps); per-probe Gauss quadrature on the device"}
     progress(f"SLQ log det: {out['estimate']:.6e} vs {exact:.6e} in {dt:.3f} s")
     return out
+
+
+# ---------------------------------------------------------------------------------------------
+# Backward-pass memory and runtime: the adjoint rules (App. B.2) against unrolled autodiff, i.e.
+# torch's autograd recording every iteration of a plain-torch CG (the comparison of App. B's figure
+# on backward runtime and peak memory).  The unrolled solver below is that comparison baseline only.
+
+def torch_kron3_mvm(K, sigma2, X):
+    """(K1 (x) K2 (x) K3 + sigma2 I) X for X of shape (r, m1, m2, m3), in plain torch matmuls."""
+    import torch
+    r, m1, m2, m3 = X.shape
+    Y = torch.matmul(X, K[2].t().contiguous())                              # mode 3
+    Y = torch.matmul(K[1], Y)                                               # mode 2
+    Y = torch.matmul(K[0], Y.reshape(r, m1, m2 * m3)).reshape(r, m1, m2, m3)   # mode 1
+    return Y + sigma2 * X
+
+
+def unrolled_cg(K, sigma2, B, iters):
+    """iters steps of textbook CG (x0 = 0) on (r, m1, m2, m3) blocks, every step recorded by autograd;
+    returns x and the per-step coefficients (alpha_j, beta_j) as graph tensors of shape (r,)."""
+    import torch
+    x = torch.zeros_like(B)
+    res = B
+    p = B
+    rho = (res * res).sum(dim=(1, 2, 3))
+    alphas, betas = [], []
+    for _ in range(iters):
+        q = torch_kron3_mvm(K, sigma2, p)
+        alpha = rho / (p * q).sum(dim=(1, 2, 3))
+        a4 = alpha[:, None, None, None]
+        x = x + a4 * p
+        res = res - a4 * q
+        rho_new = (res * res).sum(dim=(1, 2, 3))
+        beta = rho_new / rho
+        p = res + beta[:, None, None, None] * p
+        rho = rho_new
+        alphas.append(alpha)
+        betas.append(beta)
+    return x, alphas, betas
+
+
+def unrolled_slq_logdet(K, sigma2, Z, iters):
+    """Mean over probes of ||z||^2 e1^T log(T) e1, T the Lanczos tridiagonal built from the unrolled
+    CG's coefficients, its eigendecomposition by torch.linalg.eigh: all of it under autograd."""
+    import torch
+    _, al, be = unrolled_cg(K, sigma2, Z, iters)
+    a = torch.stack(al, 1)
+    b = torch.stack(be, 1)
+    d = torch.cat([1.0 / a[:, :1], 1.0 / a[:, 1:] + b[:, :-1] / a[:, :-1]], 1)
+    e = torch.sqrt(b[:, :-1]) / a[:, :-1]
+    T = torch.diag_embed(d) + torch.diag_embed(e, 1) + torch.diag_embed(e, -1)
+    lam, V = torch.linalg.eigh(T)
+    est = (Z * Z).sum(dim=(1, 2, 3)) * (V[:, 0, :] ** 2 * torch.log(lam)).sum(-1)
+    return est.mean()
+
+
+def _rbf_factors(pts, ell):
+    import torch
+    out = []
+    for p in pts:
+        d = p[:, None] - p[None, :]
+        out.append(torch.exp(-(d * d) / (2.0 * ell * ell)))
+    return out
+
+
+def _peak_begin():
+    import torch
+    torch.cuda.synchronize()
+    torch.cuda.reset_peak_memory_stats()
+    return torch.cuda.memory_allocated(), time.perf_counter()
+
+
+def _peak_end(base):
+    import torch
+    torch.cuda.synchronize()
+    return torch.cuda.max_memory_allocated() - base, time.perf_counter()
+
+
+def autograd_solve_pair(pts_np, ell0, s2_0, nrhs, iters=None, tol=1e-10, max_iters=4000, seed=11,
+                        run_unrolled=True):
+    """One size of the solve comparison: L = <W, A^{-1} B> with A = RBF(l) (x) RBF(l) (x) RBF(l) + s2 I,
+    gradients with respect to l, s2 and B.  The adjoint path is kron_cg_solve (FP64 CG to `tol`, or
+    exactly `iters` steps when given); the unrolled path runs as many CG steps in plain torch.
+    Peak memory is torch's allocator peak over forward + backward above what was allocated before, plus
+    (adjoint path) the operator's own device buffers (cola_op_memory)."""
+    import torch
+    from paper_2309_03060_amd import SystemSpec, kron_cg_solve, decode_info
+    dev = "cuda:0"
+    m = [len(p) for p in pts_np]
+    n = int(np.prod(m))
+    rng = np.random.default_rng(seed)
+    B0 = torch.tensor(rng.standard_normal((nrhs, n)), device=dev)
+    W0 = torch.tensor(rng.standard_normal((nrhs, n)), device=dev)
+    pts = [torch.tensor(p, device=dev) for p in pts_np]
+    out = {"dims": m, "n": n, "nrhs": nrhs}
+
+    def params():
+        ell = torch.tensor(ell0, dtype=torch.float64, device=dev, requires_grad=True)
+        s2 = torch.tensor(s2_0, dtype=torch.float64, device=dev, requires_grad=True)
+        B = B0.clone().requires_grad_(True)
+        return ell, s2, B
+
+    # adjoint rules
+    ell, s2, B = params()
+    base, t0 = _peak_begin()
+    K = _rbf_factors(pts, ell)
+    opts = dict(tol=tol, max_iters=max_iters, prec="fp64", check_every=32)
+    if iters is not None:
+        opts.update(tol=1e-30, max_iters=iters)
+    X = kron_cg_solve([SystemSpec(factors=[K], sigma2=s2)], B.reshape(-1), nrhs, **opts)
+    loss = (W0.reshape(-1) * X).sum()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    loss.backward()
+    peak, t2 = _peak_end(base)
+    node = X.grad_fn
+    rec = decode_info(node.info, nrhs)
+    k = max(r["iters"] for r in rec)
+    lib_peak = int(node.device_peak_bytes)
+    adj = {"iters": k, "status": sorted({r["status"] for r in rec}), "forward_s": round(t1 - t0, 5), "backward_s": round(t2 - t1, 5),
+           "peak_bytes": int(peak + lib_peak), "torch_peak_bytes": int(peak), "library_peak_bytes": lib_peak,
+           "grad_ell": float(ell.grad), "grad_sigma2": float(s2.grad)}
+    gB = B.grad.detach().clone()
+    del X, loss, node, K
+    out["adjoint"] = adj
+    if not run_unrolled:
+        return out
+    # unrolled autodiff through the same number of CG steps (after two untimed steps that let the
+    # BLAS library allocate its workspace, which it keeps)
+    ell, s2, B = params()
+    x, _, _ = unrolled_cg(_rbf_factors(pts, ell), s2, B.reshape(nrhs, *m), 2)
+    x.sum().backward()
+    del x
+    ell, s2, B = params()
+    base, t0 = _peak_begin()
+    K = _rbf_factors(pts, ell)
+    x, _, _ = unrolled_cg(K, s2, B.reshape(nrhs, *m), k)
+    loss = (W0.reshape(nrhs, *m) * x).sum()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    loss.backward()
+    peak, t2 = _peak_end(base)
+    unr = {"iters": k, "forward_s": round(t1 - t0, 5), "backward_s": round(t2 - t1, 5),
+           "peak_bytes": int(peak), "grad_ell": float(ell.grad), "grad_sigma2": float(s2.grad)}
+    unr["grad_B_rel_diff"] = float((B.grad - gB).abs().max() / gB.abs().max())
+    del x, loss, K
+    out["unrolled"] = unr
+    out["memory_ratio"] = round(unr["peak_bytes"] / adj["peak_bytes"], 3)
+    out["backward_speedup"] = round(unr["backward_s"] / adj["backward_s"], 3)
+    out["grad_rel_diff"] = {k2: abs(unr[k2] - adj[k2]) / abs(adj[k2]) for k2 in ("grad_ell", "grad_sigma2")}
+    return out
+
+
+def autograd_logdet_pair(pts_np, ell0, s2_0, nprobes, iters, seed=13, run_unrolled=True):
+    """One size of the log det comparison, exactly `iters` Lanczos (CG) steps per probe on both paths:
+    cola_slq_logdet + the Hutchinson gradient through the adjoint backward (X = G = Z), against
+    autograd through the unrolled CG, the tridiagonal and its eigendecomposition."""
+    import torch
+    import workloads as wl
+    from paper_2309_03060_amd import KronOperator, SystemSpec
+    dev = "cuda:0"
+    m = [len(p) for p in pts_np]
+    n = int(np.prod(m))
+    Z = torch.tensor(wl.rademacher_probes(np.random.default_rng(seed), nprobes, n), device=dev)
+    pts = [torch.tensor(p, device=dev) for p in pts_np]
+    out = {"dims": m, "n": n, "probes": nprobes, "iters": iters}
+    ell = torch.tensor(ell0, dtype=torch.float64, device=dev, requires_grad=True)
+    s2 = torch.tensor(s2_0, dtype=torch.float64, device=dev, requires_grad=True)
+    base, t0 = _peak_begin()
+    K = _rbf_factors(pts, ell)
+    op = KronOperator([SystemSpec(factors=[[k.detach() for k in K]], sigma2=float(s2_0))], prec="fp64")
+    ld, _, _, _ = op.logdet(Z.reshape(-1), nprobes, tol=1e-30, max_iters=iters)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    dfac, _, ds2, _ = op.logdet_grad(Z.reshape(-1), nprobes, tol=1e-30, max_iters=iters)
+    torch.autograd.backward(K, dfac[0][0])
+    peak, t2 = _peak_end(base)
+    lib_peak = op.memory()[1]
+    op.close()
+    out["adjoint"] = {"forward_s": round(t1 - t0, 5), "backward_s": round(t2 - t1, 5),
+                      "peak_bytes": int(peak + lib_peak), "torch_peak_bytes": int(peak),
+                      "library_peak_bytes": int(lib_peak), "logdet": float(ld[0]),
+                      "grad_ell": float(ell.grad), "grad_sigma2": float(ds2[0])}
+    del K, dfac
+    if not run_unrolled:
+        return out
+    ell = torch.tensor(ell0, dtype=torch.float64, device=dev, requires_grad=True)
+    s2 = torch.tensor(s2_0, dtype=torch.float64, device=dev, requires_grad=True)
+    unrolled_slq_logdet(_rbf_factors(pts, ell), s2, Z.reshape(nprobes, *m), 2).backward()   # library workspaces
+    ell.grad = None
+    s2.grad = None
+    base, t0 = _peak_begin()
+    K = _rbf_factors(pts, ell)
+    ldu = unrolled_slq_logdet(K, s2, Z.reshape(nprobes, *m), iters)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ldu.backward()
+    peak, t2 = _peak_end(base)
+    out["unrolled"] = {"forward_s": round(t1 - t0, 5), "backward_s": round(t2 - t1, 5), "peak_bytes": int(peak),
+                       "logdet": float(ldu.detach()), "grad_ell": float(ell.grad), "grad_sigma2": float(s2.grad)}
+    del K, ldu
+    out["memory_ratio"] = round(out["unrolled"]["peak_bytes"] / out["adjoint"]["peak_bytes"], 3)
+    out["backward_speedup"] = round(out["unrolled"]["backward_s"] / out["adjoint"]["backward_s"], 3)
+    out["grad_sigma2_rel_diff"] = abs(out["unrolled"]["grad_sigma2"] - out["adjoint"]["grad_sigma2"]) / abs(
+        out["adjoint"]["grad_sigma2"])
+    return out
+
+
+def run_autograd_sweep(args):
+    """Backward runtime and peak memory against CG steps (64^3 operator) and against problem size
+    (m^3, m = 16 .. 96, solved to 1e-10) for A^{-1} b, and against steps for log det.  The unrolled
+    path is skipped where its predicted memory (about 12 stored vectors per step) exceeds 96 GB."""
+    import workloads as wl
+    ell, s2 = 0.15, 0.05
+    res = {"experiment": "autograd_memory_runtime",
+           "operator": "RBF(l) (x) RBF(l) (x) RBF(l) + s2 I, l = 0.15, s2 = 0.05, gradients in l, s2, b",
+           "solve_vs_steps": [], "solve_vs_size": [], "logdet_vs_steps": []}
+    pts64 = wl.config2(m=64, nrhs=1).systems[0].points
+
+    def fits(n, rows, steps):
+        return 12 * 8 * n * rows * steps <= 96e9
+
+    autograd_solve_pair(pts64, ell, s2, 1, iters=8)                     # warm-up (kernels, allocator)
+    for k in args.autograd_steps:
+        r = autograd_solve_pair(pts64, ell, s2, 1, iters=k, run_unrolled=fits(64 ** 3, 1, k))
+        res["solve_vs_steps"].append(r)
+        progress(f"autograd solve, {k} steps: adjoint {r['adjoint']['peak_bytes'] / 2**20:.1f} MiB "
+                 f"{r['adjoint']['backward_s']:.4f} s; unrolled "
+                 + (f"{r['unrolled']['peak_bytes'] / 2**20:.1f} MiB {r['unrolled']['backward_s']:.4f} s"
+                    if "unrolled" in r else "skipped"))
+    for mm in args.autograd_sizes:
+        pts = wl.config2(m=mm, nrhs=1).systems[0].points
+        probe = autograd_solve_pair(pts, ell, s2, 1, tol=1e-10, run_unrolled=False)
+        k = probe["adjoint"]["iters"]
+        r = autograd_solve_pair(pts, ell, s2, 1, tol=1e-10, run_unrolled=fits(mm ** 3, 1, k))
+        res["solve_vs_size"].append(r)
+        progress(f"autograd solve, {mm}^3 ({k} steps): adjoint {r['adjoint']['peak_bytes'] / 2**20:.1f} MiB; "
+                 + (f"unrolled {r['unrolled']['peak_bytes'] / 2**20:.1f} MiB" if "unrolled" in r else "skipped"))
+    autograd_logdet_pair(pts64, ell, s2, 8, 8)                         # warm-up of the log det path
+    for k in args.autograd_logdet_steps:
+        r = autograd_logdet_pair(pts64, ell, s2, 8, k, run_unrolled=fits(64 ** 3, 8, k))
+        res["logdet_vs_steps"].append(r)
+        progress(f"autograd log det, {k} steps: adjoint {r['adjoint']['peak_bytes'] / 2**20:.1f} MiB; "
+                 + (f"unrolled {r['unrolled']['peak_bytes'] / 2**20:.1f} MiB" if "unrolled" in r else "skipped"))
+    return res
 
 
 def progress(msg):
@@ -593,6 +843,9 @@ def main():
         return
     if args.counters:
         run_counters(args)
+        return
+    if args.autograd:
+        print(json.dumps(run_autograd_sweep(args)))
         return
     if args.workload == "c3":
         print(json.dumps(run_uneven_batch(args)))

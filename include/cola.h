@@ -91,6 +91,17 @@ int32_t cola_op_create(const cola_system_desc* systems, int32_t nsys, int32_t pr
  * device first).  NULL is accepted. */
 int32_t cola_op_destroy(cola_op_t op);
 
+/* Device memory held by the operator (App. B: the adjoint rules keep the
+ * backward pass's memory independent of the number of solver iterations;
+ * this is how that is measured).  *live_bytes: bytes of every device buffer
+ * the operator and its internal sub-operators own right now (factor copies,
+ * CG workspace, gradient and log-det buffers); *peak_bytes: the largest value
+ * live_bytes has reached since creation or the last reset (summed over the
+ * sub-operators, so an upper bound when they peaked at different times).
+ * Either pointer may be NULL; reset_peak != 0 sets the peak to the current
+ * live bytes after reading it.  Host-side bookkeeping only: no device call. */
+int32_t cola_op_memory(cola_op_t op, int64_t* live_bytes, int64_t* peak_bytes, int32_t reset_peak);
+
 /* Total unknowns summed over systems (n_total) and number of systems. */
 int32_t cola_op_size(cola_op_t op, int64_t* n_total, int32_t* nsys);
 

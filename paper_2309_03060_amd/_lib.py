@@ -38,7 +38,7 @@ ENGINE_BY_NAME = {"fused_cg": 1, "gemm2": 2, "gemm3": 3, "slab": 4, "resident": 
 PREC_BY_NAME = {"fp64": COLA_PREC_FP64, "fp32": COLA_PREC_FP32,
                 "bf16": COLA_PREC_BF16, "bf16x3": COLA_PREC_BF16X3}
 
-EXPORTED = ("cola_op_create", "cola_op_destroy", "cola_op_size", "cola_kron_matvec",
+EXPORTED = ("cola_op_create", "cola_op_destroy", "cola_op_memory", "cola_op_size", "cola_kron_matvec",
             "cola_cg_solve", "cola_cg_solve_backward", "cola_eig_solve", "cola_slq_logdet", "cola_autotune",
             "cola_op_set_engine", "cola_profile_enable", "cola_profile_read", "cola_status_string")
 
@@ -80,6 +80,7 @@ def lib():
         vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
         L.cola_op_create.argtypes = [ctypes.POINTER(SystemDesc), i32, i32, vp, ctypes.POINTER(vp)]
         L.cola_op_destroy.argtypes = [vp]
+        L.cola_op_memory.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), i32]
         L.cola_op_size.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i32)]
         L.cola_kron_matvec.argtypes = [vp, vp, vp, i32, i32, i32, vp]
         L.cola_cg_solve.argtypes = [vp, vp, vp, i32, ctypes.POINTER(SolveOpts), vp, vp]

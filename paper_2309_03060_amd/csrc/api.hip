@@ -23,6 +23,33 @@
 
 using namespace cola;
 
+namespace cola {
+
+int32_t dev_alloc(cola_op_s* op, void** p, size_t bytes) {
+    if (bytes == 0) bytes = 16;
+    if (hipMalloc(p, bytes) != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return COLA_ERR_OOM;
+    }
+    op->dev_sizes[*p] = bytes;
+    op->dev_live += bytes;
+    op->dev_peak = std::max(op->dev_peak, op->dev_live);
+    return COLA_OK;
+}
+
+void dev_free(cola_op_s* op, void* p) {
+    if (!p) return;
+    auto it = op->dev_sizes.find(p);
+    if (it != op->dev_sizes.end()) {
+        op->dev_live -= it->second;
+        op->dev_sizes.erase(it);
+    }
+    (void)hipFree(p);
+}
+
+}  // namespace cola
+
 namespace {
 
 #define HIP_TRY(expr)                                      \
@@ -33,21 +60,12 @@ namespace {
 
 inline hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
-int32_t alloc_bytes(void** p, size_t bytes) {
-    if (bytes == 0) bytes = 16;
-    if (hipMalloc(p, bytes) != hipSuccess) {
-        *p = nullptr;
-        (void)hipGetLastError();
-        return COLA_ERR_OOM;
-    }
-    return COLA_OK;
-}
-
-void free_ws(Workspace& w) {
+void free_ws(cola_op_s* op) {
+    Workspace& w = op->ws;
     void* ptrs[] = {w.vx, w.vr, w.vp, w.vq, w.inter[0], w.inter[1], w.r64, w.x64, w.b64, w.partials,
                     w.counters, w.cg, w.outer, w.cnt};
     for (void* p : ptrs)
-        if (p) (void)hipFree(p);
+        if (p) dev_free(op, p);
     if (w.host_flag) (void)hipHostFree(w.host_flag);
     w = Workspace();
 }
@@ -70,31 +88,31 @@ int32_t ensure_ws(cola_op_s* op, int nrhs, hipStream_t st) {
     Workspace& w = op->ws;
     if (w.nrhs >= nrhs) return COLA_OK;
     destroy_graphs(op);
-    free_ws(w);
+    free_ws(op);
     const size_t vec = (size_t)nrhs * (size_t)op->nmax * sizeof(double);
     int32_t rc = COLA_OK;
-    rc |= alloc_bytes(&w.vx, vec);
-    rc |= alloc_bytes(&w.vr, vec);
-    rc |= alloc_bytes(&w.vp, vec);
-    rc |= alloc_bytes(&w.vq, vec);
-    rc |= alloc_bytes(&w.inter[0], vec * op->Jmax);
-    rc |= alloc_bytes(&w.inter[1], vec * op->Jmax);
-    rc |= alloc_bytes((void**)&w.r64, vec);
-    rc |= alloc_bytes((void**)&w.x64, vec);
-    rc |= alloc_bytes((void**)&w.b64, vec);
+    rc |= dev_alloc(op, &w.vx, vec);
+    rc |= dev_alloc(op, &w.vr, vec);
+    rc |= dev_alloc(op, &w.vp, vec);
+    rc |= dev_alloc(op, &w.vq, vec);
+    rc |= dev_alloc(op, &w.inter[0], vec * op->Jmax);
+    rc |= dev_alloc(op, &w.inter[1], vec * op->Jmax);
+    rc |= dev_alloc(op, (void**)&w.r64, vec);
+    rc |= dev_alloc(op, (void**)&w.x64, vec);
+    rc |= dev_alloc(op, (void**)&w.b64, vec);
     w.part_stride = max_blocks_per_rhs(op);
-    rc |= alloc_bytes((void**)&w.partials, sizeof(double) * (size_t)nrhs * w.part_stride);
-    rc |= alloc_bytes((void**)&w.counters, sizeof(uint32_t) * (size_t)nrhs);
-    rc |= alloc_bytes((void**)&w.cg, sizeof(CgState) * (size_t)nrhs);
-    rc |= alloc_bytes((void**)&w.outer, sizeof(OuterState) * (size_t)nrhs);
-    rc |= alloc_bytes((void**)&w.cnt, sizeof(SolveCounters));
+    rc |= dev_alloc(op, (void**)&w.partials, sizeof(double) * (size_t)nrhs * w.part_stride);
+    rc |= dev_alloc(op, (void**)&w.counters, sizeof(uint32_t) * (size_t)nrhs);
+    rc |= dev_alloc(op, (void**)&w.cg, sizeof(CgState) * (size_t)nrhs);
+    rc |= dev_alloc(op, (void**)&w.outer, sizeof(OuterState) * (size_t)nrhs);
+    rc |= dev_alloc(op, (void**)&w.cnt, sizeof(SolveCounters));
     if (rc != COLA_OK) {
-        free_ws(w);
+        free_ws(op);
         return COLA_ERR_OOM;
     }
     if (hipHostMalloc((void**)&w.host_flag, sizeof(int32_t) * 4, hipHostMallocDefault) != hipSuccess) {
         (void)hipGetLastError();
-        free_ws(w);
+        free_ws(op);
         return COLA_ERR_OOM;
     }
     w.nrhs = nrhs;
@@ -448,13 +466,13 @@ int32_t ensure_fused(cola_op_s* op) {
     if (op->fused_slots) return COLA_OK;
     // three barrier-slot sets per block, then the time-out flag
     const size_t bytes = sizeof(double) * 3 * (size_t)op->fused_max_blocks + sizeof(uint32_t);
-    int32_t rc = alloc_bytes((void**)&op->fused_slots, bytes);
+    int32_t rc = dev_alloc(op, (void**)&op->fused_slots, bytes);
     for (int b = 0; b < 2 && rc == COLA_OK; ++b)
         if (hipEventCreateWithFlags(&op->fused_done[b], hipEventDisableTiming) != hipSuccess) rc = COLA_ERR_HIP;
     if (rc == COLA_OK && hipMemset(op->fused_slots, 0, bytes) != hipSuccess) rc = COLA_ERR_HIP;
     if (rc != COLA_OK) {               // leave the path off rather than half set up
         (void)hipGetLastError();
-        if (op->fused_slots) (void)hipFree(op->fused_slots);
+        if (op->fused_slots) dev_free(op, op->fused_slots);
         op->fused_slots = nullptr;
         op->fused_max_blocks = 0;
     }
@@ -714,7 +732,7 @@ void free_resident(cola_op_s* op) {
     void* ptrs[] = {op->res_sys, op->res_order, op->res_x, op->res_r, op->res_p, op->res_t64, op->res_st,
                     op->res_queue};
     for (void* p : ptrs)
-        if (p) (void)hipFree(p);
+        if (p) dev_free(op, p);
     op->res_sys = nullptr;
     op->res_order = nullptr;
     op->res_x = op->res_r = op->res_p = nullptr;
@@ -731,14 +749,14 @@ int32_t ensure_resident(cola_op_s* op, int nrhs, hipStream_t st) {
     const int64_t nitems = (int64_t)nsys * nrhs;
     const size_t vec = (size_t)nrhs * op->n_total;
     int32_t rc = COLA_OK;
-    rc |= alloc_bytes(&op->res_sys, sizeof(ResSys) * nsys);
-    rc |= alloc_bytes((void**)&op->res_order, sizeof(int32_t) * nitems);
-    rc |= alloc_bytes((void**)&op->res_x, sizeof(float) * vec);
-    rc |= alloc_bytes((void**)&op->res_r, sizeof(float) * vec);
-    rc |= alloc_bytes((void**)&op->res_p, sizeof(float) * vec);
-    rc |= alloc_bytes((void**)&op->res_t64, sizeof(double) * vec);
-    rc |= alloc_bytes((void**)&op->res_st, sizeof(CgState) * nitems);
-    rc |= alloc_bytes((void**)&op->res_queue, sizeof(uint32_t) * 4);
+    rc |= dev_alloc(op, &op->res_sys, sizeof(ResSys) * nsys);
+    rc |= dev_alloc(op, (void**)&op->res_order, sizeof(int32_t) * nitems);
+    rc |= dev_alloc(op, (void**)&op->res_x, sizeof(float) * vec);
+    rc |= dev_alloc(op, (void**)&op->res_r, sizeof(float) * vec);
+    rc |= dev_alloc(op, (void**)&op->res_p, sizeof(float) * vec);
+    rc |= dev_alloc(op, (void**)&op->res_t64, sizeof(double) * vec);
+    rc |= dev_alloc(op, (void**)&op->res_st, sizeof(CgState) * nitems);
+    rc |= dev_alloc(op, (void**)&op->res_queue, sizeof(uint32_t) * 4);
     if (rc != COLA_OK) {
         free_resident(op);
         return COLA_ERR_OOM;
@@ -934,8 +952,8 @@ int32_t cola_op_create(const cola_system_desc* systems, int32_t nsys, int32_t pr
         if (s.F != 2 || s.J != 1 || s.dims[0] > kResMax || s.dims[1] > kResMax) op->resident_ok = false;
     (void)hipDeviceGetAttribute(&op->num_cus, hipDeviceAttributeMultiprocessorCount, op->device);
 
-    int32_t rc = alloc_bytes((void**)&op->fac64, sizeof(double) * fac);
-    if (rc == COLA_OK && dg > 0) rc = alloc_bytes((void**)&op->diag64, sizeof(double) * dg);
+    int32_t rc = dev_alloc(op, (void**)&op->fac64, sizeof(double) * fac);
+    if (rc == COLA_OK && dg > 0) rc = dev_alloc(op, (void**)&op->diag64, sizeof(double) * dg);
     if (rc != COLA_OK) {
         cola_op_destroy(op);
         return rc;
@@ -970,11 +988,11 @@ int32_t cola_op_create(const cola_system_desc* systems, int32_t nsys, int32_t pr
     }
     // working copies
     if (prec != COLA_PREC_FP64) {
-        rc = alloc_bytes((void**)&op->fac32, sizeof(float) * fac);
-        if (rc == COLA_OK && dg > 0) rc = alloc_bytes((void**)&op->diag32, sizeof(float) * dg);
+        rc = dev_alloc(op, (void**)&op->fac32, sizeof(float) * fac);
+        if (rc == COLA_OK && dg > 0) rc = dev_alloc(op, (void**)&op->diag32, sizeof(float) * dg);
         if (rc == COLA_OK && (prec == COLA_PREC_BF16 || prec == COLA_PREC_BF16X3)) {
             op->nsplit = (prec == COLA_PREC_BF16) ? 1 : 3;
-            rc = alloc_bytes((void**)&op->facbf, sizeof(__bf16) * fac * op->nsplit);
+            rc = dev_alloc(op, (void**)&op->facbf, sizeof(__bf16) * fac * op->nsplit);
         }
         if (rc != COLA_OK) {
             cola_op_destroy(op);
@@ -1012,14 +1030,14 @@ int32_t ensure_eig(cola_op_s* op, hipStream_t st) {
         }
     }
     double *vt = nullptr, *q = nullptr, *work = nullptr, *off = nullptr;
-    int32_t rc = alloc_bytes((void**)&op->eig_lam, sizeof(double) * lam_total);
-    rc |= alloc_bytes((void**)&vt, sizeof(double) * vec_total);
-    rc |= alloc_bytes((void**)&q, sizeof(double) * vec_total);
-    rc |= alloc_bytes((void**)&work, sizeof(double) * nmax * nmax);
-    rc |= alloc_bytes((void**)&off, sizeof(double) * 2);
+    int32_t rc = dev_alloc(op, (void**)&op->eig_lam, sizeof(double) * lam_total);
+    rc |= dev_alloc(op, (void**)&vt, sizeof(double) * vec_total);
+    rc |= dev_alloc(op, (void**)&q, sizeof(double) * vec_total);
+    rc |= dev_alloc(op, (void**)&work, sizeof(double) * nmax * nmax);
+    rc |= dev_alloc(op, (void**)&off, sizeof(double) * 2);
     auto cleanup = [&]() {
         for (void* p : {(void*)vt, (void*)q, (void*)work, (void*)off})
-            if (p) (void)hipFree(p);
+            if (p) dev_free(op, p);
     };
     if (rc != COLA_OK) {
         (void)hipStreamSynchronize(st);
@@ -1058,7 +1076,7 @@ int32_t ensure_eig(cola_op_s* op, hipStream_t st) {
         if (op->eig_qt) cola_op_destroy(op->eig_qt);
         if (op->eig_q) cola_op_destroy(op->eig_q);
         op->eig_qt = op->eig_q = nullptr;
-        (void)hipFree(op->eig_lam);
+        dev_free(op, op->eig_lam);
         op->eig_lam = nullptr;
     }
     return rc;
@@ -1073,10 +1091,10 @@ int32_t cola_eig_solve(cola_op_t op, const double* B, double* X, int32_t nrhs, v
     const int64_t need = (int64_t)nrhs * op->n_total;
     if (op->eig_tmp_elems < need) {
         (void)hipStreamSynchronize(st);
-        if (op->eig_tmp) (void)hipFree(op->eig_tmp);
+        if (op->eig_tmp) dev_free(op, op->eig_tmp);
         op->eig_tmp = nullptr;
         op->eig_tmp_elems = 0;
-        if (alloc_bytes((void**)&op->eig_tmp, sizeof(double) * need) != COLA_OK) return COLA_ERR_OOM;
+        if (dev_alloc(op, (void**)&op->eig_tmp, sizeof(double) * need) != COLA_OK) return COLA_ERR_OOM;
         op->eig_tmp_elems = need;
     }
     rc = cola_kron_matvec(op->eig_qt, B, op->eig_tmp, nrhs, COLA_F64, COLA_PREC_FP64, stream);
@@ -1091,13 +1109,29 @@ int32_t cola_eig_solve(cola_op_t op, const double* B, double* X, int32_t nrhs, v
     return cola_kron_matvec(op->eig_q, op->eig_tmp, X, nrhs, COLA_F64, COLA_PREC_FP64, stream);
 }
 
+int32_t cola_op_memory(cola_op_t op, int64_t* live_bytes, int64_t* peak_bytes, int32_t reset_peak) {
+    if (!op) return COLA_ERR_INVALID_ARG;
+    int64_t live = (int64_t)op->dev_live, peak = (int64_t)op->dev_peak;
+    for (cola_op_s* sub : {op->eig_qt, op->eig_q}) {
+        if (!sub) continue;
+        int64_t l = 0, p = 0;
+        cola_op_memory(sub, &l, &p, reset_peak);
+        live += l;
+        peak += p;
+    }
+    if (live_bytes) *live_bytes = live;
+    if (peak_bytes) *peak_bytes = peak;
+    if (reset_peak) op->dev_peak = op->dev_live;
+    return COLA_OK;
+}
+
 int32_t cola_op_destroy(cola_op_t op) {
     if (!op) return COLA_OK;
     (void)hipDeviceSynchronize();
     destroy_graphs(op);
     if (op->cap_stream) (void)hipStreamDestroy(op->cap_stream);
     free_resident(op);
-    free_ws(op->ws);
+    free_ws(op);
     if (op->eig_qt) cola_op_destroy(op->eig_qt);
     if (op->eig_q) cola_op_destroy(op->eig_q);
     for (hipEvent_t e : op->fused_done)
@@ -1105,7 +1139,7 @@ int32_t cola_op_destroy(cola_op_t op) {
     void* ptrs[] = {op->fac64, op->fac32, op->facbf, op->diag64, op->diag32, op->grad_buf, op->eig_lam,
                     op->eig_tmp, op->fused_slots, op->slq_buf};
     for (void* p : ptrs)
-        if (p) (void)hipFree(p);
+        if (p) dev_free(op, p);
     delete op;
     return COLA_OK;
 }
@@ -1171,10 +1205,10 @@ int32_t cola_slq_logdet(cola_op_t op, const double* Z, int32_t nprobes, double t
     const size_t hist_elems = (size_t)nprobes * 2 * (size_t)max_iters;
     const size_t need = hist_elems + (size_t)nprobes;              // history, then per-probe estimates
     if (op->slq_elems < need) {
-        if (op->slq_buf) (void)hipFree(op->slq_buf);
+        if (op->slq_buf) dev_free(op, op->slq_buf);
         op->slq_buf = nullptr;
         op->slq_elems = 0;
-        rc = alloc_bytes((void**)&op->slq_buf, need * sizeof(double));
+        rc = dev_alloc(op, (void**)&op->slq_buf, need * sizeof(double));
         if (rc != COLA_OK) return rc;
         op->slq_elems = need;
     }

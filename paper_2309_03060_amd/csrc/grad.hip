@@ -215,13 +215,10 @@ int32_t grad_system(cola_op_s* op, const SysInfo& s, const double* X, const doub
                     partial = (double*)op->ws.vq;
                 } else {
                     if (op->grad_buf_elems < need) {
-                        if (op->grad_buf) (void)hipFree(op->grad_buf);
+                        dev_free(op, op->grad_buf);
                         op->grad_buf = nullptr;
                         op->grad_buf_elems = 0;
-                        if (hipMalloc((void**)&op->grad_buf, need * sizeof(double)) != hipSuccess) {
-                            (void)hipGetLastError();
-                            return COLA_ERR_OOM;
-                        }
+                        if (dev_alloc(op, (void**)&op->grad_buf, need * sizeof(double)) != COLA_OK) return COLA_ERR_OOM;
                         op->grad_buf_elems = need;
                     }
                     partial = op->grad_buf;

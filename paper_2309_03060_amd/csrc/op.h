@@ -151,9 +151,16 @@ struct cola_op_s {
     std::vector<std::array<int64_t, 3>> eig_lam_off;
     double* eig_tmp = nullptr;
     int64_t eig_tmp_elems = 0;
+    // device memory held by this op's own allocations (bytes), and its high-water mark
+    std::map<void*, size_t> dev_sizes;
+    size_t dev_live = 0, dev_peak = 0;
 };
 
 namespace cola {
 // Allocate (or keep) the per-op workspace for nrhs right-hand sides.
 int32_t ensure_workspace(cola_op_s* op, int nrhs, hipStream_t st);
+// Device allocations owned by op, counted in its live and peak bytes
+// (dev_alloc returns COLA_ERR_OOM and sets *p = nullptr on failure).
+int32_t dev_alloc(cola_op_s* op, void** p, size_t bytes);
+void dev_free(cola_op_s* op, void* p);
 }

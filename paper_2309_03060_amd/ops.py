@@ -231,6 +231,13 @@ class KronOperator:
         L.check("cola_op_set_engine",
                 self.lib.cola_op_set_engine(self.handle, L.ENGINE_BY_NAME[name], 1 if enable else 0))
 
+    def memory(self, reset_peak: bool = False):
+        """(live, peak) bytes of device memory held by this operator (cola_op_memory)."""
+        live, peak = ctypes.c_int64(), ctypes.c_int64()
+        L.check("cola_op_memory", self.lib.cola_op_memory(self.handle, ctypes.byref(live), ctypes.byref(peak),
+                                                          1 if reset_peak else 0))
+        return live.value, peak.value
+
     def profile_enable(self, on: bool = True):
         L.check("cola_profile_enable", self.lib.cola_profile_enable(self.handle, 1 if on else 0))
 
@@ -289,6 +296,7 @@ class KronSolve(torch.autograd.Function):
         opts.update(meta.get("backward_opts", {}))
         Lam, dfac, ddiag, ds2, info = op.solve_backward(X, gX.contiguous().to(torch.float64), meta["nrhs"], **opts)
         ctx.backward_info = info
+        ctx.device_peak_bytes = op.memory()[1]     # the operator's buffers over forward and backward
         grads = [None, Lam, ds2]
         for s in dfac:
             for row in s:
