@@ -21,6 +21,10 @@ lowprec  bf16 / fp32 rounding emulator (diagnostic; App. C.3 context)
 slq      log det by stochastic Lanczos quadrature with the tridiagonal taken
          from CG coefficients, Kronecker closed forms of log det and
          Tr(A^{-1}) (App. A "Derived functions"; App. C base-case table)
+precond  preconditioned CG (Jacobi from the exact Kronecker diagonal rule,
+         Kronecker-eigen of the first term), Hutchinson and doubly
+         stochastic diagonal estimators with their per-entry variances
+         (App. A "Diagonal"; Sec. 3.3; App. B.1)
 
 Conventions: vec is row-major (C order), so (K1 (x) K2) x = vec(K1 X K2^T)
 with X = x.reshape(n1, n2), matching numpy.kron and the row-major form of the
