@@ -120,6 +120,13 @@ int32_t cola_kron_matvec(cola_op_t op, const void* X, void* Y, int32_t nrhs,
 #define COLA_REFINE_RESTART  1  /* classical refinement: restarted inner CG solves to inner_tol,
                                    FP64 residual between sweeps (at most max_sweeps sweeps)        */
 
+/* preconditioner (cola_solve_opts.precond; FP64 solves only) ------------- */
+#define COLA_PRECOND_NONE     0  /* plain CG */
+#define COLA_PRECOND_JACOBI   1  /* M = Diag(A), exact by the Sum and Kronecker diagonal rules (App. A) */
+#define COLA_PRECOND_KRON_EIG 2  /* M = (first Kronecker term) + c I with c = Tr(A - first term) / n,
+                                    applied exactly by the Kronecker eigen rules (App. A); for one term
+                                    plus sigma2 I, M = A and CG ends after one step */
+
 /* Solve options. */
 typedef struct {
     double  tol;          /* target relative residual ||b - A x|| / ||b|| per RHS, > 0 */
@@ -134,6 +141,13 @@ typedef struct {
                              iterations per sweep, device-side early exit), which
                              makes the call safe under stream capture           */
     int32_t refine;       /* COLA_REFINE_RELIABLE or COLA_REFINE_RESTART (prec != FP64) */
+    int32_t precond;      /* COLA_PRECOND_*; anything but NONE needs prec == COLA_PREC_FP64
+                             (else COLA_ERR_UNSUPPORTED).  Preconditioned CG takes the
+                             textbook recurrence (z = M^{-1} r, beta = r.z / r_old.z_old,
+                             p = z + beta p) and stops on ||b - A x|| <= tol ||b|| as
+                             plain CG does; the first call sets M up (Jacobi: one pass
+                             over the diagonal rules; Kronecker-eigen: the first term's
+                             factor eigendecompositions, waiting on the stream). */
 } cola_solve_opts;
 
 /* Per (system, RHS) outcome, written to DEVICE memory in stream order. */
@@ -207,6 +221,30 @@ int32_t cola_cg_solve_backward(cola_op_t op, const double* X, const double* G, i
  * max_iters allocates workspace. */
 int32_t cola_slq_logdet(cola_op_t op, const double* Z, int32_t nprobes, double tol, int32_t max_iters,
                         double* X, double* logdet, double* est, cola_solve_info* info, void* stream);
+
+/* Diag(A) of every system, exactly: Diag(A + B) = Diag(A) + Diag(B) and
+ * Diag(A (x) B) = vec(Diag(A) Diag(B)^T) (App. A, diagonal rules; row-major
+ * vec), plus d and sigma2.  out: device FP64, n_total entries packed by system
+ * (system i at its offset, as one right-hand side of cola_cg_solve).  O(n) per
+ * term; enqueued on `stream`. */
+int32_t cola_op_diagonal(cola_op_t op, double* out, void* stream);
+
+/* probe estimators of Diag(A) (cola_diag_estimate.mode) */
+#define COLA_DIAG_HUTCHINSON 0   /* (1/N) sum_j z_j . A z_j, every probe shared by all terms (Sec. 3.3) */
+#define COLA_DIAG_DOUBLY     1   /* (1/N) sum_j sum_i z_ij . A_i z_ij over the Kronecker terms A_i, a
+                                    probe set of its own per term, plus the exact d + sigma2 (App. B.1) */
+
+/* Stochastic estimate of Diag(A) from MVMs with probe vectors (any entries
+ * of identity covariance, e.g. +-1), all in FP64 on the device.
+ *   Z:    device FP64 probes.  HUTCHINSON: packed like the right-hand sides of
+ *         cola_cg_solve with nrhs = nprobes (system i: nprobes vectors of n_i).
+ *         DOUBLY: system i holds nterms_i * nprobes vectors of n_i, term-major
+ *         (term j's nprobes vectors together), systems in order.
+ *   out:  device FP64, n_total entries packed by system (as cola_op_diagonal).
+ * The sum's terms are applied one at a time through the same MVM kernels.
+ * Enqueued on `stream`; the first call for a given nprobes allocates workspace. */
+int32_t cola_diag_estimate(cola_op_t op, const double* Z, int32_t nprobes, int32_t mode, double* out,
+                           void* stream);
 
 /* Direct solve X = A^{-1} B of single-term systems A = K_1 (x) .. (x) K_F +
  * sigma2 * I by the Kronecker eigenvalue rules (App. A: the eigenvectors of a

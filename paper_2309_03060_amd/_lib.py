@@ -34,11 +34,14 @@ COLA_REFINE_RESTART = 1
 REFINE_BY_NAME = {"reliable": COLA_REFINE_RELIABLE, "restart": COLA_REFINE_RESTART}
 
 ENGINE_BY_NAME = {"fused_cg": 1, "gemm2": 2, "gemm3": 3, "slab": 4, "resident": 5}
+PRECOND_BY_NAME = {"none": 0, "jacobi": 1, "kron_eig": 2}
+DIAG_MODE_BY_NAME = {"hutchinson": 0, "doubly": 1}
 
 PREC_BY_NAME = {"fp64": COLA_PREC_FP64, "fp32": COLA_PREC_FP32,
                 "bf16": COLA_PREC_BF16, "bf16x3": COLA_PREC_BF16X3}
 
 EXPORTED = ("cola_op_create", "cola_op_destroy", "cola_op_memory", "cola_op_size", "cola_kron_matvec",
+            "cola_op_diagonal", "cola_diag_estimate",
             "cola_cg_solve", "cola_cg_solve_backward", "cola_eig_solve", "cola_slq_logdet", "cola_autotune",
             "cola_op_set_engine", "cola_profile_enable", "cola_profile_read", "cola_status_string")
 
@@ -52,7 +55,7 @@ class SystemDesc(ctypes.Structure):
 class SolveOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iters", ctypes.c_int32), ("prec", ctypes.c_int32),
                 ("inner_tol", ctypes.c_double), ("max_sweeps", ctypes.c_int32),
-                ("check_every", ctypes.c_int32), ("refine", ctypes.c_int32)]
+                ("check_every", ctypes.c_int32), ("refine", ctypes.c_int32), ("precond", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -87,6 +90,8 @@ def lib():
         L.cola_cg_solve_backward.argtypes = [vp, vp, vp, i32, ctypes.POINTER(SolveOpts), vp,
                                              ctypes.POINTER(vp), ctypes.POINTER(vp), vp, vp, vp]
         L.cola_eig_solve.argtypes = [vp, vp, vp, i32, vp]
+        L.cola_op_diagonal.argtypes = [vp, vp, vp]
+        L.cola_diag_estimate.argtypes = [vp, vp, i32, i32, vp, vp]
         L.cola_slq_logdet.argtypes = [vp, vp, i32, dbl, i32, vp, vp, vp, vp, vp]
         L.cola_autotune.argtypes = [vp, i32, vp]
         L.cola_op_set_engine.argtypes = [vp, i32, i32]

@@ -18,6 +18,7 @@
 #include "op.h"
 #include "resident.h"
 #include "slab.h"
+#include "pcg.h"
 #include "slq.h"
 #include "vector.h"
 
@@ -651,11 +652,161 @@ int32_t run_cg(cola_op_s* op, const SysInfo& s, int prec, int nrhs, T* x, T* r, 
     return COLA_OK;
 }
 
+int32_t ensure_eig(cola_op_s* op, hipStream_t st);
+
+// Scratch of the Kronecker-eigen transforms (at least `need` doubles).
+int32_t ensure_eig_tmp(cola_op_s* op, int64_t need, hipStream_t st) {
+    if (op->eig_tmp_elems >= need) return COLA_OK;
+    (void)hipStreamSynchronize(st);
+    if (op->eig_tmp) dev_free(op, op->eig_tmp);
+    op->eig_tmp = nullptr;
+    op->eig_tmp_elems = 0;
+    if (dev_alloc(op, (void**)&op->eig_tmp, sizeof(double) * need) != COLA_OK) return COLA_ERR_OOM;
+    op->eig_tmp_elems = need;
+    return COLA_OK;
+}
+
+// One system's operator as plain pointers into the FP64 master copy.
+DiagArgs diag_args(const cola_op_s* op, const SysInfo& s) {
+    DiagArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.J = s.J;
+    a.F = s.Fv;
+    for (int k = 0; k < 3; ++k) {
+        a.dims[k] = s.dims[k];
+        a.fac[k] = k < s.Fv ? op->fac64 + s.fac_off[k] : nullptr;
+    }
+    a.dvec = s.diag_off >= 0 ? op->diag64 + s.diag_off : nullptr;
+    a.sigma2 = s.sigma2;
+    a.n = s.n;
+    return a;
+}
+
+// Set up a preconditioner once per op: the Jacobi inverse diagonal of every
+// system, or the first term's Kronecker eigendecomposition and the shift c of
+// M = (first term) + c I per system (c = Tr(A - first term) / n).
+int32_t ensure_precond(cola_op_s* op, int kind, hipStream_t st) {
+    if (kind == COLA_PRECOND_JACOBI) {
+        if (op->pc_dinv) return COLA_OK;
+        int32_t rc = dev_alloc(op, (void**)&op->pc_dinv, sizeof(double) * op->n_total);
+        if (rc != COLA_OK) return rc;
+        for (const SysInfo& s : op->sys)
+            HIP_TRY(kron_diagonal(diag_args(op, s), op->pc_dinv + s.vec_off, true, st));
+        return COLA_OK;
+    }
+    int32_t rc = ensure_eig(op, st);
+    if (rc != COLA_OK) return rc;
+    if (op->pc_shift.size() == op->sys.size()) return COLA_OK;
+    double* dev = op->ws.partials;                 // nsys doubles of scratch (before any solve uses it)
+    std::vector<double> host(op->sys.size());
+    for (size_t i = 0; i < op->sys.size(); ++i) {
+        HIP_TRY(trace_shift(diag_args(op, op->sys[i]), dev, st));
+        HIP_TRY(hipMemcpyAsync(&host[i], dev, sizeof(double), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+    }
+    op->pc_shift = host;
+    return COLA_OK;
+}
+
+// z = (first term + c I)^{-1} r for one system: two FP64 Kronecker MVMs with the
+// eigenvector factors and one scaling by 1 / (eigenvalue products + c).
+int32_t apply_kron_eig(cola_op_s* op, size_t si, int nrhs, const double* r, double* z, hipStream_t st) {
+    const SysInfo& s = op->sys[si];
+    double* y = op->eig_tmp;
+    for (int step = 0; step < 2; ++step) {
+        cola_op_s* sub = step == 0 ? op->eig_qt : op->eig_q;
+        int32_t rc = ensure_ws(sub, nrhs, st);
+        if (rc != COLA_OK) return rc;
+        PassArgs a = base_args(sub);
+        a.epi = EPI_MATVEC;
+        a.Ep = step == 0 ? (const void*)r : (const void*)y;
+        rc = enqueue_mvm(sub, sub->sys[si], COLA_PREC_FP64, nrhs, a.Ep, nullptr, step == 0 ? (void*)y : (void*)z,
+                         a, st);
+        if (rc != COLA_OK) return rc;
+        if (step == 0) {
+            const double* lam[3] = {nullptr, nullptr, nullptr};
+            for (int k = 0; k < s.Fv; ++k) lam[k] = op->eig_lam + op->eig_lam_off[si][k];
+            HIP_TRY(eig_scale(y, y, nrhs, s.Fv, s.dims, lam, op->pc_shift[si], st));
+        }
+    }
+    return COLA_OK;
+}
+
+// Preconditioned CG in FP64 (textbook recurrence): the MVM pass forms
+// p = z + beta p and the step length as in plain CG, the update kernel moves x
+// and r and decides convergence on ||r||, then z = M^{-1} r and r.z give the
+// next beta.  Direct launches; the host polls the active count every
+// check_every iterations.
+int32_t run_pcg(cola_op_s* op, const SysInfo& s, const double* B, double* X, int nrhs, const cola_solve_opts* o,
+                cola_solve_info* info, hipStream_t st) {
+    Workspace& w = op->ws;
+    const int64_t n = s.n;
+    const int ps = (int)w.part_stride;
+    const size_t si = (size_t)(&s - op->sys.data());
+    int32_t rc = ensure_precond(op, o->precond, st);
+    if (rc != COLA_OK) return rc;
+    if (o->precond == COLA_PRECOND_KRON_EIG) {
+        rc = ensure_eig_tmp(op, (int64_t)nrhs * n, st);
+        if (rc != COLA_OK) return rc;
+    }
+    double* x = (double*)w.vx;
+    double* r = (double*)w.vr;
+    double* p = (double*)w.vp;
+    double* q = (double*)w.vq;
+    double* z = w.r64;
+    const double* dinv = o->precond == COLA_PRECOND_JACOBI ? op->pc_dinv + s.vec_off : nullptr;
+    const int vb = vec_blocks_per_rhs(n);
+    auto precondition = [&]() -> int32_t {
+        if (!dinv) {
+            const int32_t rc2 = apply_kron_eig(op, si, nrhs, r, z, st);
+            if (rc2 != COLA_OK) return rc2;
+        }
+        ProfScope ps2(op->prof, "pcg_precond_dot", st);
+        HIP_TRY(pcg_precond_dot(r, z, dinv, n, nrhs, w.cg, w.partials, ps, w.counters, w.cnt, vb, st));
+        return COLA_OK;
+    };
+    HIP_TRY(fill_i32(&w.cnt->num_active, 0, 1, st));
+    HIP_TRY(cg_prepare<double>(B, r, x, p, n, nrhs, nullptr, w.cg, o->tol, o->max_iters, 0.0, w.partials, ps,
+                               w.counters, w.cnt, st));
+    rc = precondition();
+    if (rc != COLA_OK) return rc;
+    for (int it = 0; it < o->max_iters; ++it) {
+        if (o->check_every > 0 && it > 0 && it % o->check_every == 0) {
+            int32_t active = 0;
+            rc = poll_flag(op, &w.cnt->num_active, st, &active);
+            if (rc != COLA_OK) return rc;
+            if (active <= 0) break;
+        }
+        PassArgs a = base_args(op);
+        a.cg = w.cg;
+        a.gate = &w.cg->active;
+        a.gate_stride = (int32_t)(sizeof(CgState) / sizeof(int32_t));
+        a.epi = EPI_CG;
+        a.Ep = p;
+        a.Er = z;
+        a.Epout = p;
+        rc = enqueue_mvm(op, s, COLA_PREC_FP64, nrhs, p, z, q, a, st);
+        if (rc != COLA_OK) return rc;
+        {
+            ProfScope ps2(op->prof, "pcg_update", st);
+            HIP_TRY(pcg_update(x, r, p, q, n, nrhs, w.cg, w.partials, ps, w.counters, w.cnt, vb, st));
+        }
+        rc = precondition();
+        if (rc != COLA_OK) return rc;
+    }
+    HIP_TRY(pcg_finish(w.cg, nrhs, st));
+    if (X) HIP_TRY(copy_f64(x, X, (int64_t)nrhs * n, st));
+    if (info) HIP_TRY(write_info(info, nullptr, w.cg, nrhs, st));
+    return COLA_OK;
+}
+
 int32_t solve_system(cola_op_s* op, const SysInfo& s, const double* B, double* X, int nrhs,
                      const cola_solve_opts* o, cola_solve_info* info, hipStream_t st) {
     Workspace& w = op->ws;
     const int64_t n = s.n;
     const int ps = (int)w.part_stride;
+    if (o->prec == COLA_PREC_FP64 && o->precond != COLA_PRECOND_NONE)
+        return run_pcg(op, s, B, X, nrhs, o, info, st);
     if (o->prec == COLA_PREC_FP64) {
         HIP_TRY(fill_i32(&w.cnt->num_active, 0, 1, st));
         double* r = (double*)w.vr;
@@ -849,6 +1000,8 @@ bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 int32_t check_opts(const cola_op_s* op, const cola_solve_opts* o) {
     if (!o) return COLA_ERR_INVALID_ARG;
     if (!finite_pos(o->tol) || o->max_iters < 1 || o->check_every < 0) return COLA_ERR_INVALID_ARG;
+    if (o->precond < COLA_PRECOND_NONE || o->precond > COLA_PRECOND_KRON_EIG) return COLA_ERR_INVALID_ARG;
+    if (o->precond != COLA_PRECOND_NONE && o->prec != COLA_PREC_FP64) return COLA_ERR_UNSUPPORTED;
     if (o->prec != COLA_PREC_FP64) {
         if (o->prec != op->prec) return COLA_ERR_INVALID_ARG;
         if (!finite_pos(o->inner_tol) || o->inner_tol >= 1.0) return COLA_ERR_INVALID_ARG;
@@ -1016,8 +1169,6 @@ int32_t cola_op_create(const cola_system_desc* systems, int32_t nsys, int32_t pr
 namespace {
 int32_t ensure_eig(cola_op_s* op, hipStream_t st) {
     if (op->eig_q) return COLA_OK;
-    for (const SysInfo& s : op->sys)
-        if (s.J != 1 || s.diag_off >= 0) return COLA_ERR_UNSUPPORTED;
     int64_t nmax = 1, lam_total = 0, vec_total = 0;
     op->eig_lam_off.assign(op->sys.size(), {0, 0, 0});
     for (size_t i = 0; i < op->sys.size(); ++i) {
@@ -1083,20 +1234,67 @@ int32_t ensure_eig(cola_op_s* op, hipStream_t st) {
 }
 }  // namespace
 
+int32_t cola_op_diagonal(cola_op_t op, double* out, void* stream) {
+    if (!op || !out) return COLA_ERR_INVALID_ARG;
+    hipStream_t st = S(stream);
+    for (const SysInfo& s : op->sys) HIP_TRY(kron_diagonal(diag_args(op, s), out + s.vec_off, false, st));
+    return COLA_OK;
+}
+
+int32_t cola_diag_estimate(cola_op_t op, const double* Z, int32_t nprobes, int32_t mode, double* out,
+                           void* stream) {
+    if (!op || !Z || !out || nprobes < 1) return COLA_ERR_INVALID_ARG;
+    if (mode != COLA_DIAG_HUTCHINSON && mode != COLA_DIAG_DOUBLY) return COLA_ERR_INVALID_ARG;
+    hipStream_t st = S(stream);
+    int32_t rc = ensure_ws(op, nprobes, st);
+    if (rc != COLA_OK) return rc;
+    double* Q = (double*)op->ws.vq;                  // nprobes * nmax doubles
+    const double scale = 1.0 / nprobes;
+    int64_t zoff = 0;                                 // doubles of Z consumed by earlier systems
+    for (const SysInfo& s : op->sys) {
+        double* o = out + s.vec_off;
+        if (mode == COLA_DIAG_HUTCHINSON) {
+            const double* Zs = Z + (int64_t)nprobes * s.vec_off;
+            PassArgs a = base_args(op);
+            a.epi = EPI_MATVEC;
+            a.Ep = Zs;
+            rc = enqueue_mvm(op, s, COLA_PREC_FP64, nprobes, Zs, nullptr, Q, a, st);
+            if (rc != COLA_OK) return rc;
+            HIP_TRY(probe_accumulate(Zs, Q, s.n, nprobes, scale, o, false, st));
+            continue;
+        }
+        // the diagonal part is exact; every Kronecker term gets its own probes
+        DiagArgs da = diag_args(op, s);
+        da.J = 0;
+        HIP_TRY(kron_diagonal(da, o, false, st));
+        for (int j = 0; j < s.J; ++j) {
+            SysInfo t = s;                            // term j alone: one term, no diagonal
+            t.J = 1;
+            for (int k = 0; k < s.Fv; ++k) t.fac_off[k] = s.fac_off[k] + (int64_t)j * s.dims[k] * s.dims[k];
+            t.diag_off = -1;
+            t.sigma2 = 0.0;
+            const double* Zj = Z + zoff + (int64_t)j * nprobes * s.n;
+            PassArgs a = base_args(op);
+            a.epi = EPI_MATVEC;
+            a.Ep = Zj;
+            rc = enqueue_mvm(op, t, COLA_PREC_FP64, nprobes, Zj, nullptr, Q, a, st);
+            if (rc != COLA_OK) return rc;
+            HIP_TRY(probe_accumulate(Zj, Q, s.n, nprobes, scale, o, true, st));
+        }
+        zoff += (int64_t)s.J * nprobes * s.n;
+    }
+    return COLA_OK;
+}
+
 int32_t cola_eig_solve(cola_op_t op, const double* B, double* X, int32_t nrhs, void* stream) {
     if (!op || !B || !X || nrhs < 1) return COLA_ERR_INVALID_ARG;
+    for (const SysInfo& s : op->sys)
+        if (s.J != 1 || s.diag_off >= 0) return COLA_ERR_UNSUPPORTED;
     hipStream_t st = S(stream);
     int32_t rc = ensure_eig(op, st);
     if (rc != COLA_OK) return rc;
-    const int64_t need = (int64_t)nrhs * op->n_total;
-    if (op->eig_tmp_elems < need) {
-        (void)hipStreamSynchronize(st);
-        if (op->eig_tmp) dev_free(op, op->eig_tmp);
-        op->eig_tmp = nullptr;
-        op->eig_tmp_elems = 0;
-        if (dev_alloc(op, (void**)&op->eig_tmp, sizeof(double) * need) != COLA_OK) return COLA_ERR_OOM;
-        op->eig_tmp_elems = need;
-    }
+    rc = ensure_eig_tmp(op, (int64_t)nrhs * op->n_total, st);
+    if (rc != COLA_OK) return rc;
     rc = cola_kron_matvec(op->eig_qt, B, op->eig_tmp, nrhs, COLA_F64, COLA_PREC_FP64, stream);
     if (rc != COLA_OK) return rc;
     for (size_t i = 0; i < op->sys.size(); ++i) {
@@ -1137,7 +1335,7 @@ int32_t cola_op_destroy(cola_op_t op) {
     for (hipEvent_t e : op->fused_done)
         if (e) (void)hipEventDestroy(e);
     void* ptrs[] = {op->fac64, op->fac32, op->facbf, op->diag64, op->diag32, op->grad_buf, op->eig_lam,
-                    op->eig_tmp, op->fused_slots, op->slq_buf};
+                    op->eig_tmp, op->fused_slots, op->slq_buf, op->pc_dinv};
     for (void* p : ptrs)
         if (p) dev_free(op, p);
     delete op;

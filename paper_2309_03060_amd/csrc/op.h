@@ -151,6 +151,10 @@ struct cola_op_s {
     std::vector<std::array<int64_t, 3>> eig_lam_off;
     double* eig_tmp = nullptr;
     int64_t eig_tmp_elems = 0;
+    // preconditioned CG: Jacobi inverse diagonal (n_total, packed by system) and the
+    // Kronecker-eigen preconditioner's shift per system
+    double* pc_dinv = nullptr;
+    std::vector<double> pc_shift;
     // device memory held by this op's own allocations (bytes), and its high-water mark
     std::map<void*, size_t> dev_sizes;
     size_t dev_live = 0, dev_peak = 0;

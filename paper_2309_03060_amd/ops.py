@@ -119,9 +119,11 @@ class KronOperator:
                                                               dtype, p, _stream_ptr()))
         return Y
 
-    def _opts(self, tol, max_iters, prec, inner_tol, max_sweeps, check_every, refine="reliable") -> L.SolveOpts:
+    def _opts(self, tol, max_iters, prec, inner_tol, max_sweeps, check_every, refine="reliable",
+              precond="none") -> L.SolveOpts:
         o = L.SolveOpts()
         o.refine = L.REFINE_BY_NAME[refine]
+        o.precond = L.PRECOND_BY_NAME[precond]
         o.tol = float(tol)
         o.max_iters = int(max_iters)
         o.prec = self.prec if prec is None else L.PREC_BY_NAME[prec]
@@ -132,14 +134,16 @@ class KronOperator:
 
     def solve(self, B: torch.Tensor, nrhs: int, tol: float = 1e-6, max_iters: int = 10000,
               prec: Optional[str] = None, inner_tol: float = 0.1, max_sweeps: int = 20,
-              check_every: int = 32, info: Optional[torch.Tensor] = None, refine: str = "reliable"):
-        """X = A^{-1} B (cola_cg_solve); returns (X, info tensor on device)."""
+              check_every: int = 32, info: Optional[torch.Tensor] = None, refine: str = "reliable",
+              precond: str = "none"):
+        """X = A^{-1} B (cola_cg_solve); returns (X, info tensor on device).  precond ("none",
+        "jacobi", "kron_eig") selects preconditioned CG, FP64 solves only."""
         if B.dtype != torch.float64 or not B.is_contiguous():
             raise ValueError("B must be a contiguous float64 device tensor")
         X = torch.empty_like(B)
         if info is None:
             info = torch.empty(len(self.sizes) * nrhs * 6, dtype=torch.int32, device=B.device)
-        o = self._opts(tol, max_iters, prec, inner_tol, max_sweeps, check_every, refine)
+        o = self._opts(tol, max_iters, prec, inner_tol, max_sweeps, check_every, refine, precond)
         L.check("cola_cg_solve", self.lib.cola_cg_solve(self.handle, B.data_ptr(), X.data_ptr(), nrhs,
                                                         ctypes.byref(o), info.data_ptr(), _stream_ptr()))
         return X, info
@@ -147,7 +151,7 @@ class KronOperator:
     def solve_backward(self, X: torch.Tensor, G: torch.Tensor, nrhs: int, tol: float = 1e-6,
                        max_iters: int = 10000, prec: Optional[str] = None, inner_tol: float = 0.1,
                        max_sweeps: int = 20, check_every: int = 32, want_factors: bool = True,
-                       want_diag: bool = True, refine: str = "reliable"):
+                       want_diag: bool = True, refine: str = "reliable", precond: str = "none"):
         """Adjoint backward (cola_cg_solve_backward): Lambda, dfactors, ddiag, dsigma2, info."""
         dev = X.device
         Lam = torch.empty_like(X)
@@ -175,7 +179,7 @@ class KronOperator:
                 dptrs.append(None)
         ds2 = torch.empty(len(self.systems), dtype=torch.float64, device=dev)
         info = torch.empty(len(self.sizes) * nrhs * 6, dtype=torch.int32, device=dev)
-        o = self._opts(tol, max_iters, prec, inner_tol, max_sweeps, check_every, refine)
+        o = self._opts(tol, max_iters, prec, inner_tol, max_sweeps, check_every, refine, precond)
         fa = (ctypes.c_void_p * max(1, len(ptrs)))(*ptrs) if want_factors else None
         da = (ctypes.c_void_p * len(dptrs))(*dptrs)
         L.check("cola_cg_solve_backward", self.lib.cola_cg_solve_backward(
@@ -183,6 +187,26 @@ class KronOperator:
             ctypes.cast(fa, ctypes.POINTER(ctypes.c_void_p)) if fa is not None else None,
             ctypes.cast(da, ctypes.POINTER(ctypes.c_void_p)), ds2.data_ptr(), info.data_ptr(), _stream_ptr()))
         return Lam, (dfac if want_factors else None), ddiag, ds2, info
+
+    def diagonal(self) -> torch.Tensor:
+        """Exact Diag(A) of every system, packed (cola_op_diagonal)."""
+        out = torch.empty(self.n_total, dtype=torch.float64, device="cuda")
+        L.check("cola_op_diagonal", self.lib.cola_op_diagonal(self.handle, out.data_ptr(), _stream_ptr()))
+        return out
+
+    def diag_estimate(self, Z: torch.Tensor, nprobes: int, mode: str = "hutchinson") -> torch.Tensor:
+        """Probe estimate of Diag(A) (cola_diag_estimate).  Z: float64 probes, packed per system as
+        nprobes vectors ("hutchinson") or nterms * nprobes vectors, term-major ("doubly")."""
+        if Z.dtype != torch.float64 or not Z.is_contiguous():
+            raise ValueError("Z must be a contiguous float64 device tensor")
+        per = [nprobes * n if mode == "hutchinson" else nprobes * len(s.factors) * n
+               for s, n in zip(self.systems, self.sizes)]
+        if Z.numel() != sum(per):
+            raise ValueError(f"Z has {Z.numel()} entries; {sum(per)} expected")
+        out = torch.empty(sum(self.sizes), dtype=torch.float64, device=Z.device)
+        L.check("cola_diag_estimate", self.lib.cola_diag_estimate(
+            self.handle, Z.data_ptr(), nprobes, L.DIAG_MODE_BY_NAME[mode], out.data_ptr(), _stream_ptr()))
+        return out
 
     def eig_solve(self, B: torch.Tensor, nrhs: int) -> torch.Tensor:
         """X = A^{-1} B for single-term Kronecker + sigma2 I systems by the Kronecker eigen rules
