@@ -82,6 +82,8 @@ def parse():
     ap.add_argument("--autograd-steps", type=int, nargs="+", default=[16, 32, 64, 128, 256, 512, 1024])
     ap.add_argument("--autograd-sizes", type=int, nargs="+", default=[16, 24, 32, 48, 64, 96])
     ap.add_argument("--autograd-logdet-steps", type=int, nargs="+", default=[16, 32, 64, 128, 256])
+    ap.add_argument("--check-every", type=int, default=128,
+                    help="CG iterations between host convergence checks (one fused launch each)")
     ap.add_argument("--max-iters", type=int, default=None,
                     help="cap on CG iterations per solve (default: the workload's own limit)")
     return ap.parse_args()
@@ -867,7 +869,8 @@ def main():
     B = torch.tensor(w.B[0], device=dev).reshape(-1).contiguous()
     if args.autotune:
         op.autotune(nrhs)
-    opts = dict(tol=args.tol, max_iters=args.max_iters or 20000, prec="fp32", inner_tol=0.1, check_every=32,
+    opts = dict(tol=args.tol, max_iters=args.max_iters or 20000, prec="fp32", inner_tol=0.1,
+                check_every=args.check_every,
                 refine="reliable")
 
     for _ in range(args.warmup):
@@ -926,7 +929,7 @@ def main():
                          ("mixed_fp32_restarted", dict(opts, tol=1e-6, refine="restart", inner_tol=1e-4,
                                                        max_sweeps=60)),
                          ("fp64_cg", dict(tol=1e-6, max_iters=args.max_iters or 20000, prec="fp64",
-                                          check_every=32))):
+                                          check_every=args.check_every))):
             torch.cuda.synchronize()
             t1 = time.perf_counter()
             X, info = op.solve(B, nrhs, **o)
