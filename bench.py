@@ -550,7 +550,7 @@ def run_single(args, name):
     names = ["slab23", "contract_rows", "contract_mid", "contract_last", "gemm_pack", "gemm_mode3", "gemm_mode2",
              "gemm_mode1", "update"]
     if prec == "fp64":
-        names = [k + "_fp64" for k in names]
+        names = [k + "_fp64" for k in names] + ["small_cg64"]
     kern = kernel_table(op, names)
     resid64 = kernel_table(op, ["slab23_fp64", "contract_rows_fp64", "contract_mid_fp64", "contract_last_fp64"]) \
         if prec != "fp64" else {}
@@ -587,6 +587,18 @@ def run_single(args, name):
                 "fp64_residual_passes": {k: {"avg_us": round(v["avg_us"], 2), "launches": v["launches"]}
                                          for k, v in resid64.items()},
                 "note": "bf16x3 issues 6 bf16 products per useful one; its frac is against the bf16 peak"}
+    elif "small_cg64" in kern:
+        # the whole FP64 solve of each (system, RHS) in one workgroup: one launch per solve
+        v = kern["small_cg64"]
+        flop_launch = flop_rhs_it * rhs_iters / v["launches"]
+        ach = flop_launch / (v["avg_us"] * 1e-6) / 1e12
+        roof = {"kernel": "small_cg64", "bound": "latency", "achieved": round(ach, 4), "peak": 78.6,
+                "unit": "TFLOP/s", "frac": round(ach / 78.6, 6), "traffic": None,
+                "flops_per_launch": round(flop_launch), "avg_launch_us": round(v["avg_us"], 2),
+                "us_per_iteration": round(v["avg_us"] * v["launches"] * nrhs / max(rhs_iters, 1), 3),
+                "per_kernel": per_kernel,
+                "note": "one workgroup (one CU of 256) runs the whole solve; the chip-wide FP64 peak is "
+                        "quoted for reference only: a single 4096-unknown system cannot fill the chip"}
     tts = None
     if not args.no_tts and prec != "fp64":
         res = {}

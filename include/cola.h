@@ -277,6 +277,8 @@ int32_t cola_autotune(cola_op_t op, int32_t nrhs, void* stream);
 #define COLA_ENGINE_GEMM3    3  /* dense-GEMM MVM: FP32, one-term three-mode, 256-wide modes    */
 #define COLA_ENGINE_SLAB     4  /* fused mode-2/mode-3 products of three-mode terms, modes <= 64 */
 #define COLA_ENGINE_RESIDENT 5  /* resident batched CG of many small two-mode systems           */
+#define COLA_ENGINE_SMALL64  6  /* FP64 solves of one-term two-mode systems with modes <= 64: the
+                                   whole CG of each (system, RHS) in one workgroup (no precond) */
 int32_t cola_op_set_engine(cola_op_t op, int32_t engine, int32_t enable);
 
 /* Per-kernel timing with HIP events recorded on the launch stream around

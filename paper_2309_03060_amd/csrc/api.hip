@@ -18,6 +18,7 @@
 #include "op.h"
 #include "resident.h"
 #include "slab.h"
+#include "small.h"
 #include "pcg.h"
 #include "slq.h"
 #include "vector.h"
@@ -997,6 +998,52 @@ int32_t solve_resident(cola_op_s* op, const double* B, double* X, int nrhs, cons
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
+// FP64 solves of small one-term two-mode systems: one workgroup per (system, RHS)
+// runs the whole CG; the per-system descriptors are built on the first call.
+// Per-system descriptors of the one-workgroup FP64 kernel (built when the op is created).
+int32_t build_small(cola_op_s* op) {
+    const int nsys = (int)op->sys.size();
+    std::vector<ResSys> h(nsys);
+    for (int i = 0; i < nsys; ++i) {
+        const SysInfo& s = op->sys[i];
+        h[i].n1 = (int32_t)s.dims[0];
+        h[i].n2 = (int32_t)s.dims[1];
+        h[i].n = s.n;
+        h[i].vec_off = s.vec_off;
+        h[i].k1_off = s.fac_off[0];
+        h[i].k2_off = s.fac_off[1];
+        h[i].diag_off = s.diag_off;
+        h[i].sigma2 = s.sigma2;
+    }
+    int32_t rc = dev_alloc(op, &op->small_sys, sizeof(ResSys) * nsys);
+    if (rc != COLA_OK) return rc;
+    if (hipMemcpy(op->small_sys, h.data(), sizeof(ResSys) * nsys, hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipGetLastError();
+        return COLA_ERR_HIP;
+    }
+    return COLA_OK;
+}
+
+int32_t solve_small(cola_op_s* op, const double* B, double* X, int nrhs, const cola_solve_opts* o,
+                    cola_solve_info* info, hipStream_t st) {
+    const int nsys = (int)op->sys.size();
+    SmallArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.sys = (const ResSys*)op->small_sys;
+    a.nitems = nsys * nrhs;
+    a.nrhs = nrhs;
+    a.fac64 = op->fac64;
+    a.diag64 = op->diag64;
+    a.B = B;
+    a.X = X;
+    a.tol = o->tol;
+    a.max_iters = o->max_iters;
+    a.info = info;
+    ProfScope ps(op->prof, "small_cg64", st);
+    HIP_TRY(launch_small_cg64(a, st));
+    return COLA_OK;
+}
+
 int32_t check_opts(const cola_op_s* op, const cola_solve_opts* o) {
     if (!o) return COLA_ERR_INVALID_ARG;
     if (!finite_pos(o->tol) || o->max_iters < 1 || o->check_every < 0) return COLA_ERR_INVALID_ARG;
@@ -1103,6 +1150,10 @@ int32_t cola_op_create(const cola_system_desc* systems, int32_t nsys, int32_t pr
     op->resident_ok = (prec == COLA_PREC_FP32) && nsys >= 2;
     for (const SysInfo& s : op->sys)
         if (s.F != 2 || s.J != 1 || s.dims[0] > kResMax || s.dims[1] > kResMax) op->resident_ok = false;
+    // small one-term two-mode systems: whole FP64 solves in one workgroup each
+    bool small_ok = true;
+    for (const SysInfo& s : op->sys)
+        if (s.Fv != 2 || s.J != 1 || s.dims[0] > kSmallMax || s.dims[1] > kSmallMax) small_ok = false;
     (void)hipDeviceGetAttribute(&op->num_cus, hipDeviceAttributeMultiprocessorCount, op->device);
 
     int32_t rc = dev_alloc(op, (void**)&op->fac64, sizeof(double) * fac);
@@ -1139,6 +1190,7 @@ int32_t cola_op_create(const cola_system_desc* systems, int32_t nsys, int32_t pr
             return COLA_ERR_HIP;
         }
     }
+    op->small_ok = small_ok && build_small(op) == COLA_OK;
     // working copies
     if (prec != COLA_PREC_FP64) {
         rc = dev_alloc(op, (void**)&op->fac32, sizeof(float) * fac);
@@ -1335,7 +1387,7 @@ int32_t cola_op_destroy(cola_op_t op) {
     for (hipEvent_t e : op->fused_done)
         if (e) (void)hipEventDestroy(e);
     void* ptrs[] = {op->fac64, op->fac32, op->facbf, op->diag64, op->diag32, op->grad_buf, op->eig_lam,
-                    op->eig_tmp, op->fused_slots, op->slq_buf, op->pc_dinv};
+                    op->eig_tmp, op->fused_slots, op->slq_buf, op->pc_dinv, op->small_sys};
     for (void* p : ptrs)
         if (p) dev_free(op, p);
     delete op;
@@ -1382,6 +1434,8 @@ int32_t cola_cg_solve(cola_op_t op, const double* B, double* X, int32_t nrhs, co
     if (op->resident_ok && op->use_resident && opts->prec == COLA_PREC_FP32 &&
         opts->refine == COLA_REFINE_RELIABLE)
         return solve_resident(op, B, X, nrhs, opts, info, st);
+    if (op->small_ok && op->use_small && opts->prec == COLA_PREC_FP64 && opts->precond == COLA_PRECOND_NONE)
+        return solve_small(op, B, X, nrhs, opts, info, st);
     rc = ensure_ws(op, nrhs, st);
     if (rc != COLA_OK) return rc;
     for (size_t i = 0; i < op->sys.size(); ++i) {
@@ -1438,6 +1492,10 @@ int32_t cola_cg_solve_backward(cola_op_t op, const double* X, const double* G, i
     int32_t rc = cola_cg_solve(op, G, Lambda, nrhs, opts, info, stream);
     if (rc != COLA_OK) return rc;
     hipStream_t st = S(stream);
+    // the factor contractions stage through the solve workspace, which the one-workgroup
+    // and resident solve paths do not size for nrhs right-hand sides
+    rc = ensure_ws(op, nrhs, st);
+    if (rc != COLA_OK) return rc;
     for (size_t i = 0; i < op->sys.size(); ++i) {
         const SysInfo& s = op->sys[i];
         const size_t off = (size_t)nrhs * s.vec_off;
@@ -1457,6 +1515,7 @@ int32_t cola_op_set_engine(cola_op_t op, int32_t engine, int32_t enable) {
         case COLA_ENGINE_GEMM3: op->use_gemm3 = on; break;
         case COLA_ENGINE_SLAB: op->use_slab = on; break;
         case COLA_ENGINE_RESIDENT: op->use_resident = on; break;
+        case COLA_ENGINE_SMALL64: op->use_small = on; break;
         default: return COLA_ERR_INVALID_ARG;
     }
     (void)hipDeviceSynchronize();

@@ -186,6 +186,7 @@ int32_t apply_modes_f64(cola_op_s* op, const SysInfo& s, int term, int skip, con
 
 int32_t grad_system(cola_op_s* op, const SysInfo& s, const double* X, const double* Lam, int nrhs,
                     void* const* dfactors, void* ddiag, double* dsigma2, hipStream_t st) {
+    if (op->ws.nrhs < nrhs) return COLA_ERR_INVALID_ARG;    // staging buffers must hold nrhs vectors
     if (dfactors) {
         double* Z = (double*)op->ws.inter[0];
         for (int j = 0; j < s.J; ++j)

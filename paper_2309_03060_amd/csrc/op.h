@@ -131,6 +131,9 @@ struct cola_op_s {
     double* fused_slots = nullptr;      // fused-CG barrier slots (3 * fused_max_blocks), then the time-out flag
     hipEvent_t fused_done[2] = {nullptr, nullptr};
     bool resident_ok = false;       // every system fits the resident batched kernel
+    bool small_ok = false;          // every system fits the one-workgroup FP64 kernel
+    bool use_small = true;
+    void* small_sys = nullptr;      // ResSys[nsys] of the one-workgroup FP64 kernel
     bool use_resident = true;
     int num_cus = 0;
     // resident-path workspace (allocated for res_nrhs right-hand sides)

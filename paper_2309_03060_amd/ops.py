@@ -249,7 +249,7 @@ class KronOperator:
         L.check("cola_autotune", self.lib.cola_autotune(self.handle, nrhs, _stream_ptr()))
 
     def set_engine(self, name: str, enable: bool):
-        """Switch one kernel engine on or off ("fused_cg", "gemm2", "gemm3", "slab", "resident")."""
+        """Switch one kernel engine on or off ("fused_cg", "gemm2", "gemm3", "slab", "resident", "small64")."""
         if name not in L.ENGINE_BY_NAME:
             raise ValueError(f"unknown engine {name!r}; one of {sorted(L.ENGINE_BY_NAME)}")
         L.check("cola_op_set_engine",

@@ -99,3 +99,28 @@ def test_uneven_batch_gradients_against_oracle():
             assert np.linalg.norm(got - g[0][0][f]) <= 1e-4 * np.linalg.norm(g[0][0][f]), (k, f)
         assert abs(float(ds2[k]) - g[2]) <= 1e-4 * abs(g[2]), k
     op.close()
+
+
+def test_uneven_batch_gradients_two_rhs_fresh_op():
+    """The resident solve sizes the shared workspace for one right-hand side; the adjoint backward of a
+    fresh op with two right-hand sides must still stage its factor contractions for both (regression:
+    the backward now sizes the workspace itself)."""
+    from gpu_util import make_op, pack
+    w = wl.config3(nsys=4, dmin=16, dmax=48, seed=35)
+    rng = np.random.default_rng(36)
+    nrhs = 2
+    Bs = [rng.standard_normal((nrhs, s.n)) for s in w.systems]
+    Ws = [rng.standard_normal((nrhs, s.n)) for s in w.systems]
+    op = make_op(w.systems, prec="fp32")
+    kw = dict(tol=1e-10, max_iters=8000)
+    X, _ = op.solve(pack(Bs), nrhs, **kw)
+    Lam, dfac, _, ds2, _ = op.solve_backward(X, pack(Ws), nrhs, **kw)
+    for k, s in enumerate(w.systems):
+        Xr = direct.kron_eig_solve(s.factors[0], Bs[k], s.sigma2)
+        Lr = direct.kron_eig_solve(s.factors[0], Ws[k], s.sigma2)
+        g = grad.grad_kron(s.factors, Xr, Lr)
+        for f in range(2):
+            got = dfac[k][0][f].cpu().numpy()
+            assert np.linalg.norm(got - g[0][0][f]) <= 1e-4 * np.linalg.norm(g[0][0][f]), (k, f)
+        assert abs(float(ds2[k]) - g[2]) <= 1e-4 * abs(g[2]), k
+    op.close()
