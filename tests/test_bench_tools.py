@@ -84,3 +84,40 @@ def test_measured_traffic_of_multi_iteration_launches(tmp_path, monkeypatch):
     assert bench.measured_traffic("c2", "cg_fused", 32, 2048, 4) == 512 * 400
     assert bench.source_kind("k_fused_cg") == "cg_fused" and bench.source_kind("contract_cols_f32") == "contract"
     assert bench.kernel_class("cola::(anonymous namespace)::k_fused_cg<2>(cola::FusedCgArgs)") == "k_fused_cg"
+
+
+def test_unrolled_baselines_match_oracle_on_cpu():
+    """The comparison baseline of the backward-memory experiment (plain-torch CG recorded by autograd) is
+    itself checked against the oracle on the CPU: its Kronecker MVM entry by entry, its converged solve,
+    its SLQ estimate with the same probes and steps, and its gradients on a well-conditioned operator
+    (where reverse mode through CG is stable) against the closed forms."""
+    import numpy as np
+    import torch
+    import workloads as wl
+    from oracle import direct, grad, kron, slq
+    pts = wl.config2(m=6, nrhs=1).systems[0].points
+    facs = [wl.rbf_kernel(p, 0.3) for p in pts]
+    s2 = 1.0
+    rng = np.random.default_rng(5)
+    V = rng.standard_normal((2, 216))
+    K = [torch.tensor(f) for f in facs]
+    got = bench.torch_kron3_mvm(K, s2, torch.tensor(V).reshape(2, 6, 6, 6)).reshape(2, -1).numpy()
+    np.testing.assert_allclose(got, kron.mvm([facs], V, s2), rtol=1e-13, atol=1e-13)
+    ell = torch.tensor(0.3, dtype=torch.float64, requires_grad=True)
+    sig = torch.tensor(s2, dtype=torch.float64, requires_grad=True)
+    B = rng.standard_normal((2, 216))
+    W = rng.standard_normal((2, 216))
+    x, _, _ = bench.unrolled_cg(bench._rbf_factors([torch.tensor(p) for p in pts], ell), sig,
+                                torch.tensor(B).reshape(2, 6, 6, 6), 60)
+    (torch.tensor(W).reshape(2, 6, 6, 6) * x).sum().backward()
+    X = direct.kron_eig_solve(facs, B, s2)
+    L = direct.kron_eig_solve(facs, W, s2)
+    np.testing.assert_allclose(x.detach().reshape(2, -1).numpy(), X, rtol=0, atol=1e-10 * np.abs(X).max())
+    dfac, _, ds2 = grad.grad_kron([facs], X, L)
+    dell = sum(grad.rbf_lengthscale_grad(dfac[0][k], facs[k], pts[k], 0.3) for k in range(3))
+    assert abs(float(ell.grad) - dell) <= 1e-8 * abs(dell)
+    assert abs(float(sig.grad) - ds2) <= 1e-8 * abs(ds2)
+    Z = wl.rademacher_probes(rng, 3, 216)
+    ld = bench.unrolled_slq_logdet(K, s2, torch.tensor(Z).reshape(3, 6, 6, 6), 7)
+    ref = slq.slq_logdet(lambda M: kron.mvm([facs], M, s2), Z, 7)
+    assert abs(float(ld) - ref) <= 1e-10 * abs(ref)
