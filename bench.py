@@ -384,6 +384,22 @@ def run_autograd_sweep(args):
     return res
 
 
+def copy_bandwidth(nbytes=1 << 30, reps=10):
+    """GB/s of a plain device-to-device copy (bytes read plus bytes written per second)."""
+    import torch
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda:0").fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    del src, dst
+    return 2.0 * nbytes * reps / dt / 1e9
+
+
 def progress(msg):
     """One line per finished piece of work, on stderr (the JSON result stays alone on stdout)."""
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
@@ -932,6 +948,10 @@ def main():
                                for k, v in kern.items()},
                 "fp64_residual_passes": {k: {"avg_us": round(v["avg_us"], 2), "launches": v["launches"]}
                                          for k, v in resid64.items()}}
+        copy = copy_bandwidth()
+        roof["measured_copy"] = {"GB/s": round(copy, 1), "frac_of_copy": round(achieved / copy, 4),
+                                 "note": "torch's device-to-device copy of 1 GiB (read + write bytes over "
+                                         "time), measured after the timed region: a plain streaming rate"}
 
     # mixed precision vs plain FP64 at 1e-6 true relative residual
     tts = None
