@@ -1450,7 +1450,7 @@ int32_t cola_cg_solve(cola_op_t op, const double* B, double* X, int32_t nrhs, co
 int32_t cola_slq_logdet(cola_op_t op, const double* Z, int32_t nprobes, double tol, int32_t max_iters,
                         double* X, double* logdet, double* est, cola_solve_info* info, void* stream) {
     if (!op || !Z || !logdet || nprobes < 1 || !finite_pos(tol) || max_iters < 1) return COLA_ERR_INVALID_ARG;
-    if (slq_threads_per_block(max_iters) < 1) return COLA_ERR_INVALID_ARG;
+    if (max_iters > kSlqMaxSteps) return COLA_ERR_INVALID_ARG;
     hipStream_t st = S(stream);
     int32_t rc = ensure_ws(op, nprobes, st);
     if (rc != COLA_OK) return rc;

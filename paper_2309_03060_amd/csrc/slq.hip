@@ -7,14 +7,27 @@
 // algorithms).  For a probe z, k CG iterations on A x = z give the Lanczos
 // tridiagonal T_k of the Krylov space of z through the CG-Lanczos relation:
 //     T[0][0] = 1 / alpha_0,   T[j][j] = 1 / alpha_j + beta_{j-1} / alpha_{j-1},
-//     T[j][j+1] = sqrt(beta_j) / alpha_j,
-// and z^T log(A) z ~= ||z||^2 sum_k tau_k^2 log(theta_k), with theta_k the
-// eigenvalues of T_k and tau_k the first components of its unit eigenvectors.
-// The eigenvalues come from the implicit QL iteration with shifts taken from
-// the leading 2 x 2 block; of the accumulated plane rotations only their
-// effect on the first row of the eigenvector matrix is kept (tau), so a probe
-// costs O(k^2) and three vectors of k doubles, held in LDS.  One thread per
-// probe: the probes are independent and k is at most a few thousand.
+//     T[j][j+1]^2 = beta_j / alpha_j^2,
+// and z^T log(A) z ~= ||z||^2 e1^T log(T_k) e1, the value of the k-node Gauss
+// quadrature rule (eigenvalues of T_k as nodes, squared first eigenvector
+// components as weights).
+//
+// That value is computed here without the eigendecomposition, from the
+// integral form of the logarithm of a positive definite matrix:
+//     e1^T log(T) e1 = int_0^inf [ 1 / (1 + t) - e1^T (T + t I)^{-1} e1 ] dt,
+// where e1^T (T + t I)^{-1} e1 = 1 / g_0(t) with the bottom-up pivots
+// g_{k-1} = T[k-1][k-1] + t, g_j = T[j][j] + t - T[j][j+1]^2 / g_{j+1} (all positive
+// for t >= 0).  With t = e^u the integrand, a sum of w_j (e^u / (1 + e^u) -
+// e^u / (theta_j + e^u)), is analytic in the strip |Im u| < pi and decays
+// exponentially in both directions, so the trapezoidal rule in u with step h
+// errs by about exp(-2 pi^2 / h) (h = 1/4: 1e-34) once the range covers the
+// tails; the tails are bounded from T itself: below the range the integrand is
+// about (1 - e1^T T^{-1} e1) t once t is far below the smallest eigenvalue (for
+// which 1 / Tr(T^{-1}) is a lower bound within a factor k), above it about
+// (T[0][0] - 1) / t^2 once t is far above the largest (Gershgorin bound).  The
+// nodes are independent, so a probe is one
+// workgroup with every thread on its own nodes: O(nodes * k) work in parallel
+// instead of a sequential O(k^2) eigen-iteration per probe.
 #include "slq.h"
 
 #include <cmath>
@@ -22,76 +35,66 @@
 namespace cola {
 namespace {
 
-constexpr int kQLSweeps = 64;           // QL iterations per eigenvalue before giving up (NaN)
+constexpr double kSlqStep = 0.25;       // trapezoidal step in u = log t
+constexpr double kSlqTail = 1e-18;      // absolute size of each neglected tail
+constexpr int kSlqMaxNodes = 4096;
 
-// ||z||^2 e1^T log(T) e1 for the tridiagonal of k CG iterations with
-// coefficients ab[2 j] = alpha_j, ab[2 j + 1] = beta_j; d, e, z: scratch of k.
-__device__ double log_quadrature(const double* ab, int k, double znorm2, double* d, double* e, double* z) {
-    if (k == 0) return 0.0;                          // z = 0 (no iteration ran)
-    d[0] = 1.0 / ab[0];
-    for (int j = 1; j < k; ++j) d[j] = 1.0 / ab[2 * j] + ab[2 * j - 1] / ab[2 * j - 2];
-    for (int j = 0; j + 1 < k; ++j) e[j] = sqrt(ab[2 * j + 1]) / ab[2 * j];
-    e[k - 1] = 0.0;
-    for (int j = 0; j < k; ++j) z[j] = j == 0 ? 1.0 : 0.0;
-    for (int l = 0; l < k; ++l) {
-        int sweeps = 0;
-        for (;;) {
-            int m = l;                               // the block [l, m] has no negligible coupling
-            while (m + 1 < k) {
-                const double dd = fabs(d[m]) + fabs(d[m + 1]);
-                if (fabs(e[m]) + dd == dd) break;
-                ++m;
-            }
-            if (m == l) break;                       // d[l] has converged
-            if (++sweeps > kQLSweeps) return __builtin_nan("");
-            // shift: the eigenvalue of the leading 2 x 2 block nearer d[l]
-            double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
-            double r = hypot(g, 1.0);
-            g = d[m] - d[l] + e[l] / (g + (g >= 0.0 ? r : -r));
-            double s = 1.0, c = 1.0, p = 0.0;
-            bool split = false;
-            for (int i = m - 1; i >= l; --i) {       // chase the bulge from the bottom of the block
-                const double f = s * e[i], b = c * e[i];
-                r = hypot(f, g);
-                e[i + 1] = r;
-                if (r == 0.0) {                      // the block splits here: restart on it
-                    d[i + 1] -= p;
-                    e[m] = 0.0;
-                    split = true;
-                    break;
-                }
-                s = f / r;
-                c = g / r;
-                g = d[i + 1] - p;
-                r = (d[i] - g) * s + 2.0 * c * b;
-                p = s * r;
-                d[i + 1] = g + p;
-                g = c * r - b;
-                const double zt = z[i + 1];          // the rotation acting on the first eigenvector row
-                z[i + 1] = s * z[i] + c * zt;
-                z[i] = c * z[i] - s * zt;
-            }
-            if (split) continue;
-            d[l] -= p;
-            e[l] = g;
-            e[m] = 0.0;
-        }
-    }
-    double acc = 0.0;
-    for (int j = 0; j < k; ++j) acc += z[j] * z[j] * log(d[j]);
-    return znorm2 * acc;
+// e1^T (T + t I)^{-1} e1 by the bottom-up pivots (d: diagonal, o2: squared off-diagonal)
+__device__ inline double resolvent_e1(const double* d, const double* o2, int k, double t) {
+    double g = d[k - 1] + t;
+    for (int j = k - 2; j >= 0; --j) g = d[j] + t - o2[j] / g;
+    return 1.0 / g;
 }
 
-__global__ void k_slq_probe(const double* hist, int hist_len, const CgState* cg, int nprobes, double* est) {
-    extern __shared__ double scratch[];              // 3 hist_len doubles per thread
-    const int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= nprobes) return;
-    double* d = scratch + (size_t)threadIdx.x * 3 * hist_len;
+__global__ __launch_bounds__(kThreads) void k_slq_probe(const double* hist, int hist_len, const CgState* cg,
+                                                        int nprobes, double* est) {
+    __shared__ double d[kSlqMaxSteps];
+    __shared__ double o2[kSlqMaxSteps];
+    __shared__ double pf[kSlqMaxSteps];
+    __shared__ double red[4];
+    __shared__ double s_range[2];
+    const int g = blockIdx.x;
     const CgState& st = cg[g];
     const int k = st.iters < hist_len ? st.iters : hist_len;
     const bool ok = st.status == COLA_OK || st.status == COLA_NOT_CONVERGED;   // a breakdown leaves no quadrature
-    est[g] = ok ? log_quadrature(hist + (size_t)g * 2 * hist_len, k, st.bnorm2, d, d + hist_len, d + 2 * hist_len)
-                : __builtin_nan("");
+    if (!ok || k == 0) {                                                       // k = 0: zero probe, z^T log(A) z = 0
+        if (threadIdx.x == 0) est[g] = ok ? 0.0 : __builtin_nan("");
+        return;
+    }
+    const double* ab = hist + (size_t)g * 2 * hist_len;        // (alpha_j, beta_j) pairs
+    for (int j = threadIdx.x; j < k; j += kThreads) {
+        const double a = ab[2 * j];
+        d[j] = 1.0 / a + (j > 0 ? ab[2 * j - 1] / ab[2 * j - 2] : 0.0);
+        o2[j] = j + 1 < k ? ab[2 * j + 1] / (a * a) : 0.0;
+    }
+    __syncthreads();
+    // integration range in u = log t from the tail bounds (one thread, O(k)):
+    // forward pivots pf, then backward pivots pb with (T^{-1})[j][j] = 1 / (pf_j + pb_j - d_j)
+    if (threadIdx.x == 0) {
+        pf[0] = d[0];
+        for (int j = 1; j < k; ++j) pf[j] = d[j] - o2[j - 1] / pf[j - 1];
+        double pb = d[k - 1], trace = 0.0, gmax = 0.0;
+        for (int j = k - 1; j >= 0; --j) {
+            if (j < k - 1) pb = d[j] - o2[j] / pb;
+            trace += 1.0 / (pf[j] + pb - d[j]);
+            const double rad = (j > 0 ? sqrt(o2[j - 1]) : 0.0) + (j + 1 < k ? sqrt(o2[j]) : 0.0);
+            gmax = fmax(gmax, d[j] + rad);
+        }
+        const double f0 = 1.0 / pb;                                     // e1^T T^{-1} e1
+        s_range[0] = fmin(log(kSlqTail / fmax(fabs(1.0 - f0), 1e-300)), log(1.0 / trace) - 45.0);
+        s_range[1] = log(fmax(fmax(gmax, fabs(d[0] - 1.0)), 1.0) / kSlqTail);
+    }
+    __syncthreads();
+    const double umin = s_range[0], umax = s_range[1];
+    int nodes = (int)ceil((umax - umin) / kSlqStep) + 1;
+    if (nodes > kSlqMaxNodes) nodes = kSlqMaxNodes;
+    double s = 0.0;
+    for (int i = threadIdx.x; i < nodes; i += kThreads) {
+        const double t = exp(umin + kSlqStep * i);
+        s += (1.0 / (1.0 + t) - resolvent_e1(d, o2, k, t)) * t;
+    }
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) est[g] = st.bnorm2 * kSlqStep * s;
 }
 
 // mean over the probes, summed in index order by one block
@@ -105,18 +108,10 @@ __global__ __launch_bounds__(kThreads) void k_slq_mean(const double* est, int np
 
 }  // namespace
 
-int slq_threads_per_block(int hist_len) {
-    const int t = (int)(kSlqLds / (3 * sizeof(double) * (size_t)hist_len));
-    return t < 1 ? 0 : (t > 64 ? 64 : t);
-}
-
 hipError_t slq_logdet(const double* hist, int hist_len, const CgState* cg, int nprobes, double* est,
                       double* logdet, hipStream_t s) {
-    const int tpb = slq_threads_per_block(hist_len);
-    if (tpb < 1 || nprobes < 1) return hipErrorInvalidValue;
-    const size_t lds = (size_t)tpb * 3 * hist_len * sizeof(double);
-    hipLaunchKernelGGL(k_slq_probe, dim3((unsigned)((nprobes + tpb - 1) / tpb)), dim3(tpb), lds, s, hist, hist_len,
-                       cg, nprobes, est);
+    if (hist_len < 1 || hist_len > kSlqMaxSteps || nprobes < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_slq_probe, dim3((unsigned)nprobes), dim3(kThreads), 0, s, hist, hist_len, cg, nprobes, est);
     hipLaunchKernelGGL(k_slq_mean, dim3(1), dim3(kThreads), 0, s, est, nprobes, logdet);
     return hipGetLastError();
 }
