@@ -422,9 +422,21 @@ def cpu_baseline(w, iters):
     res = ocg.cg(apply_A, B, tol=1e-30, max_iters=iters)
     dt = time.perf_counter() - t0
     rhs_iters = int(res.iters.sum())
-    return {"value": rhs_iters / dt, "unit": "RHS*iters/s", "cores": int(cores), "kind": "oracle",
-            "sample": f"numpy float64 CG on the same operator, {B.shape[0]} RHS x {iters} iterations "
-                      f"({rhs_iters} RHS*iters) in {dt:.2f} s"}
+    out = {"value": rhs_iters / dt, "unit": "RHS*iters/s", "cores": int(cores), "kind": "oracle",
+           "sample": f"numpy float64 CG on the same operator, {B.shape[0]} RHS x {iters} iterations "
+                     f"({rhs_iters} RHS*iters) in {dt:.2f} s"}
+    try:                                   # the same oracle on one core, over a shorter window
+        from threadpoolctl import threadpool_limits
+        it1 = max(2, iters // 10)
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            r1 = ocg.cg(apply_A, B, tol=1e-30, max_iters=it1)
+            d1 = time.perf_counter() - t0
+        out["single_core"] = {"value": float(r1.iters.sum()) / d1, "cores": 1,
+                              "sample": f"{B.shape[0]} RHS x {it1} iterations in {d1:.2f} s"}
+    except Exception as e:                 # threadpoolctl missing: report why
+        out["single_core"] = {"error": str(e)[:120]}
+    return out
 
 
 def kernel_table(op, names):
