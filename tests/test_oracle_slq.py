@@ -99,3 +99,24 @@ def test_probe_gradient_of_logdet_wrt_factor():
     per = np.einsum("pai,ij,pbj->pab", Lr, facs[1], Zr)
     mean, sd = per.mean(axis=0), per.std(axis=0, ddof=1) / np.sqrt(len(per))
     assert np.all(np.abs(mean - exact) <= 4.5 * sd + 1e-12)
+
+
+def test_log_quadrature_equals_integral_form():
+    """e1^T log(T) e1 = int_0^inf [1/(1+t) - e1^T (T + tI)^{-1} e1] dt for a positive definite tridiagonal
+    T (the integral form of the matrix logarithm, which the device evaluates); checked here with an
+    adaptive integrator against the eigendecomposition route, on Lanczos tridiagonals of a well and an
+    ill conditioned operator."""
+    import scipy.integrate
+    rng = np.random.default_rng(6)
+    for shift, m in ((0.5, 12), (1e-3, 40)):
+        A = _spd(rng, 60, shift)
+        d, e = slq.lanczos(lambda V: V @ A.T, rng.standard_normal(60), m)
+        T = np.diag(d) + np.diag(e, 1) + np.diag(e, -1)
+        e1 = np.zeros(len(d))
+        e1[0] = 1.0
+        f = lambda t: 1.0 / (1.0 + t) - float(np.linalg.solve(T + t * np.eye(len(d)), e1)[0])
+        # in u = log t the integrand is smooth and decays exponentially at both ends
+        val, err = scipy.integrate.quad(lambda u: f(np.exp(u)) * np.exp(u), -60.0, 60.0, limit=400,
+                                        epsabs=1e-13, epsrel=1e-12)
+        ref = slq.quadrature(d, e, np.log)
+        assert abs(val - ref) <= 1e-9 * max(1.0, abs(ref)), (shift, val, ref)
