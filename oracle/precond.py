@@ -19,7 +19,7 @@ sum_l A_kl z_k z_l, so with Gaussian z it is A_kk^2 + sum_l A_kl^2, and with
 Rademacher z (z_k^2 = 1) it is sum over l != k of A_kl^2.
 
 Preconditioned CG: the paper pairs CG and GMRES with preconditioners in its
-applications (Sec. 3.2, Sec. 3.3 and the sum-structure experiments of App. E)
+applications (Sec. 3.2, Sec. 3.3 and the sum-structure experiments of App. D.3)
 but prints no steps, so this is the textbook recurrence (Saad, Iterative Methods, Alg. 9.1)
 with x0 = 0 and a symmetric positive definite M:
 
