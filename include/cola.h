@@ -91,7 +91,7 @@ int32_t cola_op_create(const cola_system_desc* systems, int32_t nsys, int32_t pr
  * device first).  NULL is accepted. */
 int32_t cola_op_destroy(cola_op_t op);
 
-/* Device memory held by the operator (App. B: the adjoint rules keep the
+/* Device memory held by the operator (App. B.2: the adjoint rules keep the
  * backward pass's memory independent of the number of solver iterations;
  * this is how that is measured).  *live_bytes: bytes of every device buffer
  * the operator and its internal sub-operators own right now (factor copies,
