@@ -172,3 +172,38 @@ def test_c5_full_size_pcg_certified():
         iters[kind] = max(r["iters"] for r in rec)
     print("iterations:", iters, flush=True)
     op.close()
+
+
+def test_pcg_edge_cases_and_argument_checks():
+    """A zero right-hand side among others: x = 0 after zero steps with either preconditioner; an
+    unknown preconditioner or estimator mode and a wrongly sized probe block are refused."""
+    import ctypes
+    import torch
+    from paper_2309_03060_amd import ColaError
+    from paper_2309_03060_amd import _lib as L
+    from gpu_util import infos, make_op, pack, unpack
+    rng, systems = _systems(96)
+    s = systems[1]
+    B = rng.standard_normal((3, s.n))
+    B[1] = 0.0
+    op = make_op([s], prec="fp64")
+    for kind in ("jacobi", "kron_eig"):
+        X, info = op.solve(pack([B]), 3, tol=1e-10, max_iters=2000, prec="fp64", precond=kind)
+        rec = infos(info, 3)
+        Xs = unpack(X, [s], 3)[0]
+        assert rec[1]["iters"] == 0 and rec[1]["status"] == 0 and not np.any(Xs[1]), rec
+        assert all(rec[r]["status"] == 0 for r in (0, 2))
+        assert np.all(kron.relres(s.factors, Xs[[0, 2]], B[[0, 2]], s.sigma2, s.diag) <= 1e-10)
+    o = op._opts(1e-8, 100, "fp64", 0.1, 20, 32)
+    o.precond = 7
+    X = torch.empty(s.n, dtype=torch.float64, device="cuda")
+    st = op.lib.cola_cg_solve(op.handle, pack([B[:1]]).data_ptr(), X.data_ptr(), 1, ctypes.byref(o), None, None)
+    assert st == L.COLA_ERR_INVALID_ARG
+    Z = torch.ones(s.n, dtype=torch.float64, device="cuda")
+    st = op.lib.cola_diag_estimate(op.handle, Z.data_ptr(), 1, 5, X.data_ptr(), None)
+    assert st == L.COLA_ERR_INVALID_ARG
+    with pytest.raises(ValueError):
+        op.diag_estimate(Z, 1, "doubly")            # three terms need three probe sets
+    with pytest.raises(ColaError):
+        op.solve(pack([B[:1]]), 1, prec="fp64", precond="none", max_iters=0)
+    op.close()
