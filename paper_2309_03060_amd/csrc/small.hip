@@ -5,21 +5,25 @@
 // T = P K2^T (the mode-2 product of the per-mode Kronecker MVM, Table 2) fit
 // the LDS of one CU, so a whole CG solve runs inside one workgroup with no
 // kernel boundary per iteration (a multi-kernel iteration of such a system is
-// bound by launch latency, not by its 1 MFLOP).  Wave w owns rows
-// 4w .. 4w + 3 of the n1 x n2 grid and lane l column l; each thread keeps its
-// four elements of x, r and p in registers.  Per iteration:
-//   T[i][j] = sum_k P[i][k] K2[j][k]     (P read transposed: 4 rows per LDS broadcast)
-//   q[i][j] = sum_k K1[i][k] T[k][j] + (sigma2 + d) p
+// bound by launch latency, not by its 1 MFLOP).  Both mode products run on the
+// FP64 matrix cores (16 x 16 x 4 MFMA): wave w computes output tile
+// (w / 4, w % 4) of the 64 x 64 grid, and each thread keeps x, r and p of the
+// four elements its MFMA accumulator holds in registers.  Per iteration:
+//   T[i][j] = sum_k P[i][k] K2[j][k],   q[i][j] = sum_k K1[i][k] T[k][j] + (sigma2 + d) p
 // then the textbook CG step with FP64 block sums in a fixed order.  Padding
-// rows and columns hold zeros in P and the factors, so they stay zero.
+// rows and columns hold zeros in P and the factors, so they stay zero.  The
+// LDS pitches keep every MFMA operand read free of bank conflicts (one double
+// per lane per operand: a tenth of the LDS traffic per multiply-add of plain
+// FMAs fed by broadcast reads).
 #include "small.h"
 
 namespace cola {
 namespace {
 
-constexpr int kST = 1024;               // 16 waves
+constexpr int kST = 1024;               // 16 waves: wave w owns output tile (w / 4, w % 4) of 16 x 16
 constexpr int SM = kSmallMax;
-constexpr int PS = SM + 1;              // row stride of P^T (odd: spreads the transposed stores over banks)
+constexpr int PA = SM + 2;              // pitch of A operands (P, K1): a half-wave reads 16 rows x 2 columns
+constexpr int PB = SM + 16;             // pitch of B operands (K2^T, T): a half-wave reads 2 rows x 16 columns
 
 __device__ inline double block_sum_small(double v, double* red) {
     v = wave_sum(v);
@@ -34,36 +38,44 @@ __device__ inline double block_sum_small(double v, double* red) {
     return s;
 }
 
+__device__ inline doublex4 mma64(double a, double b, doublex4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
 __global__ __launch_bounds__(kST) void k_small_cg64(SmallArgs a) {
-    __shared__ double K1T[SM * SM];     // K1T[k][i] = K1[i][k]
-    __shared__ double K2T[SM * SM];     // K2T[k][j] = K2[j][k]
-    __shared__ double PT[SM * PS];      // PT[k][i] = P[i][k]
-    __shared__ double Ts[SM * SM];      // T[i][j]
+    __shared__ double K1s[SM * PA];     // K1[i][k]
+    __shared__ double K2T[SM * PB];     // K2T[k][j] = K2[j][k]
+    __shared__ double Ps[SM * PA];      // P[i][k]
+    __shared__ double Ts[SM * PB];      // T[k][j] = (P K2^T)[k][j]
     __shared__ double red[kST / 64];
     const int item = blockIdx.x;
     const ResSys sy = a.sys[item / a.nrhs];
     const int rhs = item % a.nrhs;
     const int n1 = sy.n1, n2 = sy.n2;
-    const int k1max = (n1 + 7) & ~7, k2max = (n2 + 7) & ~7;   // <= kSmallMax
+    const int k1max = (n1 + 15) & ~15, k2max = (n2 + 15) & ~15;  // four MFMA steps of depth 4 at a time;
+                                                                   // rows beyond n hold zeros
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int ti = wave >> 2, tj = wave & 3, lr = lane & 15, lk = lane >> 4;
     const int64_t base = (int64_t)a.nrhs * sy.vec_off + (int64_t)rhs * sy.n;
     const double* K1 = a.fac64 + sy.k1_off;
     const double* K2 = a.fac64 + sy.k2_off;
     for (int e = tid; e < SM * SM; e += kST) {
-        const int k = e / SM, i = e % SM;
-        K1T[e] = (k < n1 && i < n1) ? K1[i * n1 + k] : 0.0;
-        K2T[e] = (k < n2 && i < n2) ? K2[i * n2 + k] : 0.0;
+        const int r = e / SM, c = e % SM;
+        K1s[r * PA + c] = (r < n1 && c < n1) ? K1[r * n1 + c] : 0.0;
+        K2T[r * PB + c] = (r < n2 && c < n2) ? K2[c * n2 + r] : 0.0;
     }
-    for (int e = tid; e < SM * PS; e += kST) PT[e] = 0.0;
+    for (int e = tid; e < SM * PA; e += kST) Ps[e] = 0.0;
 
-    // this thread's elements: rows 4 wave + v, column lane
+    // this thread's elements: the MFMA output layout of tile (ti, tj), element v at
+    // row 16 ti + 4 v + lane / 16, column 16 tj + lane % 16
+    const int j = 16 * tj + lr;
     double x[4], r[4], p[4], dd[4];
     double bb = 0.0;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-        const int i = 4 * wave + v;
-        const bool own = i < n1 && lane < n2;
-        const int64_t e = (int64_t)i * n2 + lane;
+        const int i = 16 * ti + 4 * v + lk;
+        const bool own = i < n1 && j < n2;
+        const int64_t e = (int64_t)i * n2 + j;
         r[v] = own ? a.B[base + e] : 0.0;
         x[v] = 0.0;
         p[v] = r[v];
@@ -78,37 +90,37 @@ __global__ __launch_bounds__(kST) void k_small_cg64(SmallArgs a) {
     else if (bb <= tol2) status = COLA_OK;                  // includes b = 0: x = 0 after zero iterations
     while (status == COLA_NOT_CONVERGED && iters < a.max_iters) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) PT[lane * PS + 4 * wave + v] = p[v];
+        for (int v = 0; v < 4; ++v) Ps[(16 * ti + 4 * v + lk) * PA + j] = p[v];
         __syncthreads();                                     // P complete
-        // k runs to a multiple of 8: rows k >= n2 of P^T and K2^T hold zeros
-        double t[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int kb = 0; kb < k2max; kb += 8) {
+        doublex4 acc = {0.0, 0.0, 0.0, 0.0};
+        for (int kb = 0; kb < k2max; kb += 16) {             // T = P K2^T
+            double av[4], bv[4];
 #pragma unroll
-            for (int kk = 0; kk < 8; ++kk) {
-                const int k = kb + kk;
-                const double kv = K2T[k * SM + lane];
-#pragma unroll
-                for (int v = 0; v < 4; ++v) t[v] = fma(PT[k * PS + 4 * wave + v], kv, t[v]);
+            for (int s = 0; s < 4; ++s) {
+                av[s] = Ps[(16 * ti + lr) * PA + kb + 4 * s + lk];
+                bv[s] = K2T[(kb + 4 * s + lk) * PB + j];
             }
+#pragma unroll
+            for (int s = 0; s < 4; ++s) acc = mma64(av[s], bv[s], acc);
         }
 #pragma unroll
-        for (int v = 0; v < 4; ++v) Ts[(4 * wave + v) * SM + lane] = t[v];
+        for (int v = 0; v < 4; ++v) Ts[(16 * ti + 4 * v + lk) * PB + j] = acc[v];
         __syncthreads();                                     // T complete
-        // rows k >= n1 of T and K1^T hold zeros (P^T has zero columns there)
-        double q[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int kb = 0; kb < k1max; kb += 8) {
+        acc = doublex4{0.0, 0.0, 0.0, 0.0};
+        for (int kb = 0; kb < k1max; kb += 16) {             // K1 T
+            double av[4], bv[4];
 #pragma unroll
-            for (int kk = 0; kk < 8; ++kk) {
-                const int k = kb + kk;
-                const double tv = Ts[k * SM + lane];
-#pragma unroll
-                for (int v = 0; v < 4; ++v) q[v] = fma(K1T[k * SM + 4 * wave + v], tv, q[v]);
+            for (int s = 0; s < 4; ++s) {
+                av[s] = K1s[(16 * ti + lr) * PA + kb + 4 * s + lk];
+                bv[s] = Ts[(kb + 4 * s + lk) * PB + j];
             }
+#pragma unroll
+            for (int s = 0; s < 4; ++s) acc = mma64(av[s], bv[s], acc);
         }
-        double pq = 0.0;
+        double q[4], pq = 0.0;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            q[v] = fma(dd[v], p[v], q[v]);
+            q[v] = fma(dd[v], p[v], acc[v]);
             pq += p[v] * q[v];
         }
         pq = block_sum_small(pq, red);
@@ -135,8 +147,8 @@ __global__ __launch_bounds__(kST) void k_small_cg64(SmallArgs a) {
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-        const int i = 4 * wave + v;
-        if (i < n1 && lane < n2) a.X[base + (int64_t)i * n2 + lane] = x[v];
+        const int i = 16 * ti + 4 * v + lk;
+        if (i < n1 && j < n2) a.X[base + (int64_t)i * n2 + j] = x[v];
     }
     if (a.info && tid == 0) {
         cola_solve_info o;
