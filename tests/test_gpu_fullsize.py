@@ -40,14 +40,17 @@ def _certify(s, X, B, info, tol):
     return rr
 
 
-def test_c2_full_solve_bench_configuration():
-    """64^3 RBF operator, 32 RHS, FP32 CG with FP64 reliable updates to 1e-5 (the timed workload)."""
+@pytest.mark.parametrize("check_every", [128, 32])
+def test_c2_full_solve_bench_configuration(check_every):
+    """64^3 RBF operator, 32 RHS, FP32 CG with FP64 reliable updates to 1e-5 (the timed workload): 128
+    fused CG iterations per launch and host check as the benchmark runs it, and 32."""
     from gpu_util import infos, make_op, pack, unpack
     w = wl.config2()
     s = w.systems[0]
     op = make_op([s], prec="fp32")
     op.autotune(32)
-    X, info = op.solve(pack(w.B), 32, tol=1e-5, max_iters=20000, prec="fp32", inner_tol=0.1, check_every=32)
+    X, info = op.solve(pack(w.B), 32, tol=1e-5, max_iters=20000, prec="fp32", inner_tol=0.1,
+                       check_every=check_every)
     _certify(s, unpack(X, [s], 32)[0], w.B[0], infos(info, 32), 1e-5)
     op.close()
 
