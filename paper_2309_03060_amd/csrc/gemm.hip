@@ -13,9 +13,9 @@
 // GEMMs take their operands k-contiguous.  Block tile 256 x 256, k slice 64,
 // 8 waves (two per SIMD, so one wave's LDS and memory waits overlap the
 // other's MFMAs) each owning 128 x 64 (4 x 2 MFMA tiles); two LDS stages, the
-// next k slice loaded into registers while the current one is multiplied.
-// Block indices are mapped so that each XCD works on a contiguous group of
-// tiles that share operand panels in its L2.
+// next k slice copied from global memory straight into LDS while the current
+// one is multiplied.  Block indices are mapped so that each XCD works on a
+// contiguous group of tiles that share operand panels in its L2.
 #include "gemm.h"
 
 #include <algorithm>
@@ -31,9 +31,8 @@ namespace {
 
 constexpr int BM = 256, BN = 256, KS = 64;
 constexpr int kGT = 512;                         // threads of the GEMM kernels (8 waves)
-constexpr int KSP = KS + 8;                      // LDS row pitch (bf16): conflict-free 16-byte reads
-constexpr int kChunks = BM * KS / 8 / kGT;       // 16-byte chunks of one operand slice per thread
-constexpr int kStage = (BM + BN) * KSP;          // bf16 elements of one LDS stage (A and B slices)
+constexpr int kStage = (BM + BN) * KS;           // bf16 elements of one LDS stage (A and B slices, 128-byte rows)
+constexpr int kLdsBytes = 147456;                // two stages (131072 B) or the largest epilogue staging
 
 // Block sum over the 8 waves of a GEMM block (fixed order); valid in every thread.
 __device__ inline double block_sum8(double v, double* smem8) {
@@ -84,66 +83,106 @@ __device__ inline int xcd_linear(int b, int T) {
     return (T % 8 == 0) ? (b % 8) * (T / 8) + b / 8 : b;
 }
 
+// One k slice: start the loads of the next slice into stage N and multiply
+// the current one from stage S (A slice at the stage base, B slice
+// 2 BM KS elements further, an offset that offb already holds).  The restrict
+// qualifiers give the loads and the reads disjoint alias scopes, so the
+// compiler does not wait for the loads in flight before reading the other
+// stage.
+__device__ __attribute__((always_inline)) inline void gemm_step(
+    floatx16 (&acc)[4][2], const __bf16* __restrict__ S, __bf16* __restrict__ N, bool more, const __bf16* ga,
+    int64_t lda, uint32_t aoff, const __bf16* gb, int64_t ldb, uint32_t boff, int wave, const uint32_t (&offa)[2][4],
+    const uint32_t (&offb)[2][4]) {
+    if (more) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int rb = 8 * q + wave;                   // row block of 8 rows
+            __builtin_amdgcn_global_load_lds((const void*)(ga + (int64_t)rb * 8 * lda + aoff),
+                                             (__attribute__((address_space(3))) void*)(N + rb * 8 * KS), 16, 0, 0);
+            __builtin_amdgcn_global_load_lds((const void*)(gb + (int64_t)rb * 8 * ldb + boff),
+                                             (__attribute__((address_space(3))) void*)(N + 2 * BM * KS + rb * 8 * KS),
+                                             16, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        bf16x8 av[4], bv[2];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) av[i] = *(const bf16x8*)&S[i * 32 * KS + offa[i & 1][m]];
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj) bv[jj] = *(const bf16x8*)&S[jj * 32 * KS + offb[jj & 1][m]];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int jj = 0; jj < 2; ++jj) acc[i][jj] = mfma32(av[i], bv[jj], acc[i][jj]);
+    }
+}
+
 // acc += A_tile * B_tile^T over k in [0, nk) for this wave's 128 x 64 part.
 // abase(k0) / bbase(k0) give the (block-uniform) address of row 0, column k0
 // of the A / B tile; rows are lda / ldb elements apart and every row segment
-// is 16-byte aligned.  Each thread loads rows crow + 64 q at one per-thread
-// offset from a uniform base, keeping the address arithmetic scalar.
+// is 16-byte aligned.  Slices move from global memory straight into LDS
+// (global_load_lds_dwordx4: lane l of a wave writes 16 bytes at LDS base +
+// 16 l), one slice ahead of the one being multiplied, so no register staging
+// and no LDS store instructions sit between the MFMAs.  LDS rows are 128
+// bytes with no padding; 16-byte chunk c of row rho holds k chunk
+// c ^ swz(rho), swz(rho) = (rho ^ rho / 8) % 8, which keeps the MFMA operand
+// reads free of bank conflicts.  Wave w loads row blocks 8 w' + w (w' = 0..3)
+// of 8 rows each; for those rows swz = (lane / 8) ^ w.
 template <class ABase, class BBase>
 __device__ inline void gemm_tile(floatx16 (&acc)[4][2], int nk, ABase abase, int64_t lda, BBase bbase, int64_t ldb,
                                  __bf16* smem) {
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) & 7;   // scalar, range known
     const int wm = wave >> 2, wn = wave & 3;
-    const int crow = tid >> 3, ck = (tid & 7) * 8;
-    const uint32_t aoff = (uint32_t)(crow * lda + ck), boff = (uint32_t)(crow * ldb + ck);
-    const int klast = nk - KS;
-    u32x4 ra[kChunks], rb[kChunks];
-    auto load = [&](int k0) {
-        k0 = k0 < klast ? k0 : klast;                      // clamped, so the loads are unconditional
-        const __bf16* a0 = abase(k0);
-        const __bf16* b0 = bbase(k0);
+    // LDS: A slices of stages 0 and 1, then B slices of stages 0 and 1
+    __bf16* const A0 = smem;
+    __bf16* const A1 = smem + BM * KS;
+    __bf16* const B0 = smem + 2 * BM * KS;
+    const int lsw = ((lane >> 3) ^ wave) & 7;
+    const uint32_t aoff = (uint32_t)((lane >> 3) * lda + 8 * ((lane & 7) ^ lsw));
+    const uint32_t boff = (uint32_t)((lane >> 3) * ldb + 8 * ((lane & 7) ^ lsw));
+    // Operand row rho = 32 t + (lane % 32) of a 32-row MFMA tile t, logical chunk
+    // kc = 2 m + lane / 32 of k step m: swz = (lane % 8) ^ ((4 t + (lane % 32) / 8) % 8) depends on
+    // t only through its parity, so eight per-lane offsets (parity x step) per operand serve every
+    // tile and both stages; tiles add immediate offsets.
+    uint32_t offa[2][4], offb[2][4];
 #pragma unroll
-        for (int q = 0; q < kChunks; ++q) {
-            ra[q] = *(const u32x4*)(a0 + (int64_t)q * 64 * lda + aoff);
-            rb[q] = *(const u32x4*)(b0 + (int64_t)q * 64 * ldb + boff);
+    for (int par = 0; par < 2; ++par)
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const int sw = (lane & 7) ^ ((4 * par + ((lane & 31) >> 3)) & 7);
+            const uint32_t o = (uint32_t)((lane & 31) * KS + 8 * ((2 * m + (lane >> 5)) ^ sw));
+            offa[par][m] = o + (uint32_t)(wm * 128 * KS);
+            offb[par][m] = o + (uint32_t)(2 * BM * KS + wn * 64 * KS);   // relative to the A base
         }
-    };
-    auto stage = [&](int buf) {
-        __bf16* As = smem + buf * kStage;
-        __bf16* Bs = As + BM * KSP;
+    {
+        const __bf16* ga = abase(0);
+        const __bf16* gb = bbase(0);
 #pragma unroll
-        for (int q = 0; q < kChunks; ++q) {
-            *(u32x4*)&As[(crow + 64 * q) * KSP + ck] = ra[q];
-            *(u32x4*)&Bs[(crow + 64 * q) * KSP + ck] = rb[q];
+        for (int q = 0; q < 4; ++q) {
+            const int rb = 8 * q + wave;
+            __builtin_amdgcn_global_load_lds((const void*)(ga + (int64_t)rb * 8 * lda + aoff),
+                                             (__attribute__((address_space(3))) void*)(A0 + rb * 8 * KS), 16, 0, 0);
+            __builtin_amdgcn_global_load_lds((const void*)(gb + (int64_t)rb * 8 * ldb + boff),
+                                             (__attribute__((address_space(3))) void*)(B0 + rb * 8 * KS), 16, 0, 0);
         }
-    };
-    load(0);
-    stage(0);
-    __syncthreads();
-    int buf = 0;
-    for (int k0 = 0; k0 < nk; k0 += KS) {
-        load(k0 + KS);                                     // next slice (clamped on the last)
-        __builtin_amdgcn_sched_barrier(0);                 // keep the loads ahead of the MFMAs
-        const __bf16* As = smem + buf * kStage;
-        const __bf16* Bs = As + BM * KSP;
-#pragma unroll
-        for (int kk = 0; kk < KS; kk += 16) {
-            bf16x8 av[4], bv[2];
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-                av[i] = *(const bf16x8*)&As[(wm * 128 + i * 32 + (lane & 31)) * KSP + kk + 8 * (lane >> 5)];
-#pragma unroll
-            for (int j = 0; j < 2; ++j)
-                bv[j] = *(const bf16x8*)&Bs[(wn * 64 + j * 32 + (lane & 31)) * KSP + kk + 8 * (lane >> 5)];
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 2; ++j) acc[i][j] = mfma32(av[i], bv[j], acc[i][j]);
-        }
-        stage(buf ^ 1);                                    // the last one stages a slice nobody reads
-        __syncthreads();
-        buf ^= 1;
     }
+    // stage pointers swap every slice; the restrict parameters of gemm_step
+    // carry their disjointness to the compiler
+    __bf16* cur = A0;
+    __bf16* nxt = A1;
+    for (int k0 = 0; k0 < nk; k0 += KS) {
+        __builtin_amdgcn_s_waitcnt(0xF70);                 // vmcnt(0): this wave's part of slice k0 is in LDS
+        __syncthreads();                                   // all of it; the other stage no longer read
+        const bool more = k0 + KS < nk;
+        const int kn = more ? k0 + KS : k0;
+        gemm_step(acc, cur, nxt, more, abase(kn), lda, aoff, bbase(kn), ldb, boff, wave, offa, offb);
+        __bf16* t = cur;
+        cur = nxt;
+        nxt = t;
+    }
+    __syncthreads();                                       // callers reuse the LDS for their epilogues
 }
 
 __device__ inline bool rhs_active(const Gemm2Args& a, int r) {
@@ -186,7 +225,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm2_pack(Gemm2Args a) {
 
 // G1: T_r[b][j n1 + a'] = sum_b' P16[r n1 + a', b'] V_j[b, b'].
 __global__ __launch_bounds__(kGT) void k_gemm2_t(Gemm2Args a) {
-    __shared__ __attribute__((aligned(16))) __bf16 smem[2 * kStage];
+    __shared__ __attribute__((aligned(16))) __bf16 smem[kLdsBytes / 2];
     const int Mt = a.nrhs * (a.n1 / BM), Nt = a.J * (a.n2 / BN);
     const int L = xcd_linear(blockIdx.x, Mt * Nt);
     int mt, nt;
@@ -248,7 +287,7 @@ __global__ __launch_bounds__(kGT) void k_gemm2_t(Gemm2Args a) {
 // G2: q_r[a, b] = sum_(j, a') U_j[a, a'] T_r[b][j n1 + a'] + (sigma2 + d) p_r[a, b],
 // with the CG epilogue's partial p.q and the step length alpha.
 __global__ __launch_bounds__(kGT) void k_gemm2_y(Gemm2Args a) {
-    __shared__ __attribute__((aligned(16))) __bf16 smem[2 * kStage];
+    __shared__ __attribute__((aligned(16))) __bf16 smem[kLdsBytes / 2];
     __shared__ double red[8];
     const int tn = a.n2 / BN, tpr = (a.n1 / BM) * tn;
     const int L = xcd_linear(blockIdx.x, a.nrhs * tpr);
