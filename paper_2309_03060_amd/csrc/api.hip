@@ -689,10 +689,17 @@ DiagArgs diag_args(const cola_op_s* op, const SysInfo& s) {
 int32_t ensure_precond(cola_op_s* op, int kind, hipStream_t st) {
     if (kind == COLA_PRECOND_JACOBI) {
         if (op->pc_dinv) return COLA_OK;
-        int32_t rc = dev_alloc(op, (void**)&op->pc_dinv, sizeof(double) * op->n_total);
+        double* dinv = nullptr;
+        int32_t rc = dev_alloc(op, (void**)&dinv, sizeof(double) * op->n_total);
         if (rc != COLA_OK) return rc;
         for (const SysInfo& s : op->sys)
-            HIP_TRY(kron_diagonal(diag_args(op, s), op->pc_dinv + s.vec_off, true, st));
+            if (kron_diagonal(diag_args(op, s), dinv + s.vec_off, true, st) != hipSuccess) {
+                (void)hipGetLastError();
+                (void)hipStreamSynchronize(st);
+                dev_free(op, dinv);                        // not kept half filled
+                return COLA_ERR_HIP;
+            }
+        op->pc_dinv = dinv;                                // published once every system is enqueued
         return COLA_OK;
     }
     int32_t rc = ensure_eig(op, st);
@@ -1245,6 +1252,8 @@ int32_t ensure_eig(cola_op_s* op, hipStream_t st) {
     if (rc != COLA_OK) {
         (void)hipStreamSynchronize(st);
         cleanup();
+        dev_free(op, op->eig_lam);                         // a later call starts from scratch
+        op->eig_lam = nullptr;
         return COLA_ERR_OOM;
     }
     std::vector<std::array<const void*, 3>> fqt(op->sys.size()), fq(op->sys.size());
