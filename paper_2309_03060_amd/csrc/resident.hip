@@ -275,47 +275,109 @@ __global__ __launch_bounds__(kResThreads) void k_resident_cg(ResArgs a) {
 // r_lo = r; then the reliable-update decision.  Final pass (a.all_items):
 // every item without a certified residual (status not OK); a converged item
 // was certified by its last update and its x has not changed since.
-__global__ __launch_bounds__(kThreads) void k_resident_resid64(ResArgs a) {
-    __shared__ double Xs[kResMax * kResMax];
-    __shared__ double red[4];
+// FP64 residual of one item, r = b - A x, with both mode products on the FP64
+// matrix cores (v_mfma_f64_16x16x4f64; lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16], accumulator element v sits at row 4 v + l / 16, column
+// l % 16).  X stays in LDS (padded rows, zero beyond the system), the factors
+// and T = X K2^T come from L2.  Each wave computes groups of 1 x 4 output
+// tiles (16 x 64) that share the A fragment; 16 waves per item so that four
+// waves per SIMD cover each other's L2 latency.
+constexpr int kResidThreads = 1024;
+constexpr int PX = kResMax + 2;                  // pitch of X: conflict-free A-operand reads
+
+__device__ inline doublex4 mma_f64(double a, double b, doublex4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+__global__ __launch_bounds__(kResidThreads) void k_resident_resid64(ResArgs a) {
+    __shared__ double Xs[kResMax * PX];
+    __shared__ double red[kResWaves];
     const int item = blockIdx.x;
     CgState& st = a.st[item];
     if (a.all_items ? st.status == COLA_OK : !st.need_update) return;
     const ResSys sy = a.sys[item / a.nrhs];
     const int rhs = item % a.nrhs;
     const int n1 = sy.n1, n2 = sy.n2;
-    const int64_t n = sy.n;
-    const int64_t base = (int64_t)a.nrhs * sy.vec_off + (int64_t)rhs * n;
+    const int64_t base = (int64_t)a.nrhs * sy.vec_off + (int64_t)rhs * sy.n;
     const double* K1 = a.fac64 + sy.k1_off;
     const double* K2 = a.fac64 + sy.k2_off;
     const double* dgv = sy.diag_off >= 0 ? a.diag64 + sy.diag_off : nullptr;
-    for (int64_t e = threadIdx.x; e < n; e += kThreads) {
-        const double xv = a.x64[base + e] + (double)a.x[base + e];
-        a.x64[base + e] = xv;
-        a.x[base + e] = 0.f;
-        Xs[e] = xv;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int n1p = (n1 + 15) & ~15, n2p = (n2 + 15) & ~15;       // 16 x 16 tile extents
+    // fold the FP32 correction into x64 and stage X (zero in the padding)
+    for (int e = tid; e < n1p * n2p; e += kResidThreads) {
+        const int row = e / n2p, col = e % n2p;
+        double v = 0.0;
+        if (row < n1 && col < n2) {
+            const int64_t g = base + (int64_t)row * n2 + col;
+            v = a.x64[g] + (double)a.x[g];
+            a.x64[g] = v;
+            a.x[g] = 0.f;
+        }
+        Xs[row * PX + col] = v;
     }
     __syncthreads();
-    // T = X K2^T  (FP64, into the item's scratch)
-    for (int64_t e = threadIdx.x; e < n; e += kThreads) {
-        const int ia = (int)(e / n2), ib = (int)(e % n2);
-        double s = 0.0;
-        for (int l = 0; l < n2; ++l) s = __builtin_fma(Xs[ia * n2 + l], K2[ib * n2 + l], s);
-        a.t64[base + e] = s;
+    const int nt1 = n1p / 16, nt2 = n2p / 16, ng2 = (nt2 + 3) / 4;
+    // T[i][j] = sum_l X[i][l] K2[j][l]
+    for (int g = wave; g < nt1 * ng2; g += kResWaves) {
+        const int i0 = (g / ng2) * 16, j0 = (g % ng2) * 64;
+        doublex4 acc[4] = {};
+        for (int k = 0; k < n2p; k += 4) {
+            const int kk = k + lk;
+            const double av = Xs[(i0 + lr) * PX + kk];
+            double bv[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int col = j0 + 16 * t + lr;
+                bv[t] = (col < n2 && kk < n2) ? K2[(int64_t)col * n2 + kk] : 0.0;
+            }
+#pragma unroll
+            for (int t = 0; t < 4; ++t) acc[t] = mma_f64(av, bv[t], acc[t]);
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = i0 + 4 * v + lk, col = j0 + 16 * t + lr;
+                if (row < n1 && col < n2) a.t64[base + (int64_t)row * n2 + col] = acc[t][v];
+            }
     }
-    __syncthreads();
+    __syncthreads();                                    // T complete
+    // q = K1 T + (sigma2 + d) x,  r = b - q
     double rr = 0.0;
-    for (int64_t e = threadIdx.x; e < n; e += kThreads) {
-        const int ia = (int)(e / n2), ib = (int)(e % n2);
-        double s = 0.0;
-        for (int i = 0; i < n1; ++i) s = __builtin_fma(K1[ia * n1 + i], a.t64[base + (int64_t)i * n2 + ib], s);
-        const double dg = sy.sigma2 + (dgv ? dgv[e] : 0.0);
-        const double rv = a.b64[base + e] - (s + dg * Xs[e]);
-        a.r[base + e] = (float)rv;
-        rr += rv * rv;
+    for (int g = wave; g < nt1 * ng2; g += kResWaves) {
+        const int i0 = (g / ng2) * 16, j0 = (g % ng2) * 64;
+        doublex4 acc[4] = {};
+        const int arow = i0 + lr;
+        for (int k = 0; k < n1p; k += 4) {
+            const int kk = k + lk;
+            const double av = (arow < n1 && kk < n1) ? K1[(int64_t)arow * n1 + kk] : 0.0;
+            double bv[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int col = j0 + 16 * t + lr;
+                bv[t] = (col < n2 && kk < n1) ? a.t64[base + (int64_t)kk * n2 + col] : 0.0;
+            }
+#pragma unroll
+            for (int t = 0; t < 4; ++t) acc[t] = mma_f64(av, bv[t], acc[t]);
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = i0 + 4 * v + lk, col = j0 + 16 * t + lr;
+                if (row < n1 && col < n2) {
+                    const int64_t e = (int64_t)row * n2 + col;
+                    const double dg = sy.sigma2 + (dgv ? dgv[e] : 0.0);
+                    const double rv = a.b64[base + e] - (acc[t][v] + dg * Xs[row * PX + col]);
+                    a.r[base + e] = (float)rv;
+                    rr += rv * rv;
+                }
+            }
     }
-    rr = block_sum(rr, red);
-    if (threadIdx.x == 0) {
+    rr = block_sum8(rr, red);
+    if (tid == 0) {
         st.rho_true = rr;
         if (!a.all_items) reliable_finish(st, a.cnt);
     }
@@ -330,7 +392,7 @@ hipError_t launch_resident_cg(const ResArgs& a, int grid, hipStream_t s) {
     return hipGetLastError();
 }
 hipError_t launch_resident_resid64(const ResArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL(k_resident_resid64, dim3(a.nitems), dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL(k_resident_resid64, dim3(a.nitems), dim3(kResidThreads), 0, s, a);
     return hipGetLastError();
 }
 
