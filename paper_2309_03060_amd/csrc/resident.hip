@@ -147,6 +147,39 @@ __global__ __launch_bounds__(kResThreads) void k_resident_cg(ResArgs a) {
         for (int j = 0; j < 16; ++j) rr[j] = j < ncol ? a.r[base + (int64_t)orow * n2 + ocol + j] : 0.f;
         __syncthreads();
 
+        // Factor chunks in the order the iteration consumes them (K2 column
+        // chunks, then K1 column chunks, then K2 again for the next iteration):
+        // every thread holds its four entries of the next chunk in registers,
+        // loaded while the current chunk's MFMAs run.  Entry u of a chunk is
+        // e = tid + u * kResThreads, row e / KC, column e % KC of the chunk.
+        const int nc2 = n2k / KC, nc1 = n1k / KC;
+        int cnext = 0;                                  // chunk the registers hold
+        float fpre[4];
+        auto fetch = [&](int c) {
+            const bool second = c >= nc2;
+            const float* K = second ? K1 : K2;
+            const int nk = second ? n1 : n2;
+            const int npad = second ? n1p : n2p;
+            const int c0 = (second ? c - nc2 : c) * KC;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int e = tid + u * kResThreads, rb = e / KC, kc = e % KC;
+                fpre[u] = (e < npad * KC && rb < nk && c0 + kc < nk) ? K[rb * nk + c0 + kc] : 0.f;
+            }
+        };
+        auto fetch_next = [&]() {
+            cnext = cnext + 1 == nc2 + nc1 ? 0 : cnext + 1;
+            fetch(cnext);
+        };
+        auto stage_chunk = [&](int npad) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int e = tid + u * kResThreads;
+                if (e < npad * KC) Fc[(e / KC) * FPS + e % KC] = fpre[u];
+            }
+        };
+        fetch(0);
+
         for (;;) {
             // p = r + beta p on the owned elements
             const float bf = (float)beta;
@@ -159,11 +192,9 @@ __global__ __launch_bounds__(kResThreads) void k_resident_cg(ResArgs a) {
 #pragma unroll
             for (int v = 0; v < 16; ++v) acc[v] = 0.f;
             for (int l0 = 0; l0 < n2k; l0 += KC) {
-                for (int e = tid; e < n2p * KC; e += kResThreads) {
-                    const int rb = e / KC, kc = e % KC;
-                    Fc[rb * FPS + kc] = (rb < n2 && l0 + kc < n2) ? K2[rb * n2 + l0 + kc] : 0.f;
-                }
+                stage_chunk(n2p);
                 __syncthreads();
+                fetch_next();                               // lands during this chunk's MFMAs
                 if (has_tile) {
                     const float* pa = Ps + (ti + l32) * RPS + l0 + lh;
                     const float* fb = Fc + (tj + l32) * FPS + lh;
@@ -182,11 +213,9 @@ __global__ __launch_bounds__(kResThreads) void k_resident_cg(ResArgs a) {
 #pragma unroll
             for (int v = 0; v < 16; ++v) acc[v] = 0.f;
             for (int i0 = 0; i0 < n1k; i0 += KC) {
-                for (int e = tid; e < n1p * KC; e += kResThreads) {
-                    const int ra = e / KC, kc = e % KC;
-                    Fc[ra * FPS + kc] = (ra < n1 && i0 + kc < n1) ? K1[ra * n1 + i0 + kc] : 0.f;
-                }
+                stage_chunk(n1p);
                 __syncthreads();
+                fetch_next();
                 if (has_tile) {
                     const float* fa = Fc + (ti + l32) * FPS + lh;
                     const float* tb = Ts + (i0 + lh) * RPS + tj + l32;
@@ -275,10 +304,9 @@ __global__ __launch_bounds__(kResThreads) void k_resident_cg(ResArgs a) {
 // r_lo = r; then the reliable-update decision.  Final pass (a.all_items):
 // every item without a certified residual (status not OK); a converged item
 // was certified by its last update and its x has not changed since.
-// FP64 residual of one item, r = b - A x, with both mode products on the FP64
-// matrix cores (v_mfma_f64_16x16x4f64; lane l supplies A[l % 16][l / 16] and
-// B[l / 16][l % 16], accumulator element v sits at row 4 v + l / 16, column
-// l % 16).  X stays in LDS (padded rows, zero beyond the system), the factors
+// Both mode products run on the FP64 matrix cores (v_mfma_f64_16x16x4f64;
+// lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16], accumulator
+// element v sits at row 4 v + l / 16, column l % 16).  X stays in LDS (padded rows, zero beyond the system), the factors
 // and T = X K2^T come from L2.  Each wave computes groups of 1 x 4 output
 // tiles (16 x 64) that share the A fragment; 16 waves per item so that four
 // waves per SIMD cover each other's L2 latency.
