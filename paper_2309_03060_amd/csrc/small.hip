@@ -25,16 +25,18 @@ constexpr int SM = kSmallMax;
 constexpr int PA = SM + 2;              // pitch of A operands (P, K1): a half-wave reads 16 rows x 2 columns
 constexpr int PB = SM + 16;             // pitch of B operands (K2^T, T): a half-wave reads 2 rows x 16 columns
 
+// Block sum with a single barrier.  The caller alternates between two slot
+// arrays (p.q in one, r.r in the other): between the reads of one array and
+// its next write every thread passes at least one other barrier of the
+// iteration, so no barrier is needed to protect the slots.
 __device__ inline double block_sum_small(double v, double* red) {
     v = wave_sum(v);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    __syncthreads();
     if (lane == 0) red[wave] = v;
     __syncthreads();
     double s = 0.0;
 #pragma unroll
     for (int i = 0; i < kST / 64; ++i) s += red[i];
-    __syncthreads();
     return s;
 }
 
@@ -47,7 +49,8 @@ __global__ __launch_bounds__(kST) void k_small_cg64(SmallArgs a) {
     __shared__ double K2T[SM * PB];     // K2T[k][j] = K2[j][k]
     __shared__ double Ps[SM * PA];      // P[i][k]
     __shared__ double Ts[SM * PB];      // T[k][j] = (P K2^T)[k][j]
-    __shared__ double red[kST / 64];
+    __shared__ double red_rr[kST / 64];    // slots of the b.b and r.r sums
+    __shared__ double red_pq[kST / 64];    // slots of the p.q sums
     const int item = blockIdx.x;
     const ResSys sy = a.sys[item / a.nrhs];
     const int rhs = item % a.nrhs;
@@ -82,7 +85,7 @@ __global__ __launch_bounds__(kST) void k_small_cg64(SmallArgs a) {
         dd[v] = own ? sy.sigma2 + (sy.diag_off >= 0 ? a.diag64[sy.diag_off + e] : 0.0) : 0.0;
         bb += r[v] * r[v];
     }
-    bb = block_sum_small(bb, red);
+    bb = block_sum_small(bb, red_rr);
     const double tol2 = a.tol * a.tol * bb;
     double rho = bb;
     int iters = 0, status = COLA_NOT_CONVERGED;
@@ -123,7 +126,7 @@ __global__ __launch_bounds__(kST) void k_small_cg64(SmallArgs a) {
             q[v] = fma(dd[v], p[v], acc[v]);
             pq += p[v] * q[v];
         }
-        pq = block_sum_small(pq, red);
+        pq = block_sum_small(pq, red_pq);
         if (!(pq > 0.0) || !__builtin_isfinite(pq)) {
             status = __builtin_isfinite(pq) ? COLA_ERR_NOT_SPD : COLA_ERR_NONFINITE;
             break;
@@ -136,7 +139,7 @@ __global__ __launch_bounds__(kST) void k_small_cg64(SmallArgs a) {
             r[v] = fma(-alpha, q[v], r[v]);
             rr += r[v] * r[v];
         }
-        rr = block_sum_small(rr, red);
+        rr = block_sum_small(rr, red_rr);
         ++iters;
         const double beta = rr / rho;
         rho = rr;
