@@ -24,16 +24,17 @@ constexpr int FPS = KC + 4;                      // row stride of a factor chunk
 constexpr int kResWaves = kResThreads / 64;
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
+// Sum over the 16 waves of an item's workgroup with a single barrier.  A
+// caller that sums again must use another slot array (or pass a barrier)
+// before it writes these slots again: other waves may still be reading them.
 __device__ inline double block_sum8(double v, double* smem) {
     v = wave_sum(v);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    __syncthreads();
     if (lane == 0) smem[wave] = v;
     __syncthreads();
     double s = 0.0;
 #pragma unroll
     for (int i = 0; i < kResThreads / 64; ++i) s += smem[i];
-    __syncthreads();
     return s;
 }
 
@@ -90,7 +91,9 @@ __global__ __launch_bounds__(kResThreads) void k_resident_cg(ResArgs a) {
     __shared__ __attribute__((aligned(16))) float Ps[kResMax * RPS];   // direction p
     __shared__ __attribute__((aligned(16))) float Ts[kResMax * RPS];   // T = P K2^T, then Q = K1 T
     __shared__ __attribute__((aligned(16))) float Fc[kResMax * FPS];   // factor chunk
-    __shared__ double red[kResWaves];
+    __shared__ double red_pq[kResWaves];       // slots of the p.q sums
+    __shared__ double red_rr[kResWaves];       // slots of the r.r sums (every other barrier of the
+                                               // iteration lies between one sum's reads and its next write)
     __shared__ int s_item;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int lr = lane & 15, lq = lane >> 4;
@@ -241,7 +244,7 @@ __global__ __launch_bounds__(kResThreads) void k_resident_cg(ResArgs a) {
                     qo[j] = qv;
                     mu_l += (double)pe * (double)qv;
                 }
-            const double mu = block_sum8(mu_l, red);
+            const double mu = block_sum8(mu_l, red_pq);
             if (!(mu > 0.0) || !finite_d(mu)) {
                 status = finite_d(mu) ? COLA_ERR_NOT_SPD : COLA_ERR_NONFINITE;
                 active = 0;
@@ -256,7 +259,7 @@ __global__ __launch_bounds__(kResThreads) void k_resident_cg(ResArgs a) {
                     rr[j] = __builtin_fmaf(-af, qo[j], rr[j]);
                     rho_l += (double)rr[j] * (double)rr[j];
                 }
-            const double rn = block_sum8(rho_l, red);
+            const double rn = block_sum8(rho_l, red_rr);
             ++iters;
             bool stop = false;
             if (!finite_d(rn)) {
