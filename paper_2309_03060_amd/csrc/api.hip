@@ -225,6 +225,7 @@ int32_t enqueue_mvm(cola_op_s* op, const SysInfo& s, int prec, int nrhs, const v
         g.K3 = op->fac32 + s.fac_off[2];
         g.X = (const float*)X;
         g.R = (const float*)Rpnew;
+        g.Xit = tmpl.epi == EPI_CG ? (float*)tmpl.Ex : nullptr;
         g.Z1 = (float*)op->ws.inter[0];
         g.Z2 = (float*)op->ws.inter[1];
         g.Y = (float*)Yout;
@@ -359,10 +360,12 @@ int32_t poll_flag(cola_op_s* op, const int32_t* dev, hipStream_t st, int32_t* ou
 
 // One CG iteration on prepared state (x, r, p, q are the working vectors):
 // the MVM passes (direction update fused into the first and last pass) and
-// the vector update.
+// the vector update.  defer_x: the MVM engine may take over x += alpha p
+// (applied one iteration late by its first pass; reliable-update solves only,
+// whose fold catches up a step still pending).
 template <typename T>
 int32_t enqueue_iteration(cola_op_s* op, const SysInfo& s, int prec, int nrhs, T* x, T* r, T* p, T* q,
-                          hipStream_t st) {
+                          bool defer_x, hipStream_t st) {
     Workspace& w = op->ws;
     PassArgs a = base_args(op);
     a.cg = w.cg;
@@ -372,6 +375,7 @@ int32_t enqueue_iteration(cola_op_s* op, const SysInfo& s, int prec, int nrhs, T
     a.Ep = p;
     a.Er = r;
     a.Epout = p;
+    a.Ex = defer_x ? x : nullptr;
     int32_t rc = enqueue_mvm(op, s, prec, nrhs, p, r, q, a, st);
     if (rc != COLA_OK) return rc;
     ProfScope ps(op->prof, sizeof(T) == 8 ? "update_fp64" : "update", st);
@@ -388,6 +392,7 @@ struct ReliableTail {
     const double* B;  // FP64 right-hand sides
     float* xl;        // low-precision iterate
     float* rl;        // low-precision residual
+    const float* pl;  // low-precision direction (a deferred x += alpha p is caught up from it)
 };
 
 // final == false: the reliable update of the right-hand sides that asked for
@@ -400,7 +405,7 @@ int32_t enqueue_tail(cola_op_s* op, const SysInfo& s, int nrhs, const ReliableTa
                      hipStream_t st) {
     Workspace& w = op->ws;
     if (final) HIP_TRY(mark_unverified(w.cg, nrhs, st));
-    HIP_TRY(reliable_fold<float>(t.X, t.xl, s.n, nrhs, w.cg, false, st));
+    HIP_TRY(reliable_fold<float>(t.X, t.xl, t.pl, s.n, nrhs, w.cg, false, st));
     PassArgs a = base_args(op);
     a.cg = w.cg;
     a.gate = &w.cg->need_update;
@@ -440,7 +445,8 @@ int32_t capture_chunk(cola_op_s* op, const SysInfo& s, int prec, int nrhs, T* x,
     if (hipStreamBeginCapture(op->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return COLA_ERR_HIP;
     if (op->prof.enabled) op->prof.capture_list = &out->ev;
     int32_t rc = COLA_OK;
-    for (int i = 0; i < chunk && rc == COLA_OK; ++i) rc = enqueue_iteration<T>(op, s, prec, nrhs, x, r, p, q, op->cap_stream);
+    for (int i = 0; i < chunk && rc == COLA_OK; ++i)
+        rc = enqueue_iteration<T>(op, s, prec, nrhs, x, r, p, q, tail != nullptr, op->cap_stream);
     if (rc == COLA_OK && tail) rc = enqueue_tail(op, s, nrhs, *tail, false, op->cap_stream);
     op->prof.capture_list = nullptr;
     hipGraph_t g = nullptr;
@@ -576,7 +582,7 @@ int32_t run_cg(cola_op_s* op, const SysInfo& s, int prec, int nrhs, T* x, T* r, 
     const int nchunks = (max_iters + chunk - 1) / chunk;
     auto direct_chunk = [&]() -> int32_t {
         for (int it = 0; it < chunk; ++it) {
-            int32_t rc = enqueue_iteration<T>(op, s, prec, nrhs, x, r, p, q, st);
+            int32_t rc = enqueue_iteration<T>(op, s, prec, nrhs, x, r, p, q, tail != nullptr, st);
             if (rc != COLA_OK) return rc;
         }
         if (tail) return enqueue_tail(op, s, nrhs, *tail, false, st);
@@ -846,7 +852,7 @@ int32_t solve_system(cola_op_s* op, const SysInfo& s, const double* B, double* X
         const double delta = (op->prec == COLA_PREC_BF16) ? -o->inner_tol : o->inner_tol;
         HIP_TRY(cg_prepare<float>(w.b64, rl, xl, pl, n, nrhs, nullptr, w.cg, o->tol, o->max_iters, delta,
                                   w.partials, ps, w.counters, w.cnt, st));
-        ReliableTail tail{w.x64, w.b64, xl, rl};
+        ReliableTail tail{w.x64, w.b64, xl, rl, pl};
         int32_t rc = run_cg<float>(op, s, op->prec, nrhs, xl, rl, pl, ql, o->max_iters, o->check_every, &tail, st);
         if (rc != COLA_OK) return rc;
         rc = enqueue_tail(op, s, nrhs, tail, true, st);       // final fold and true residual where stale

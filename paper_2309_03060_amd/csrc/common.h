@@ -35,6 +35,8 @@ struct CgState {
     int32_t fails;     // consecutive reliable updates after which the true residual missed tol
     int32_t updates;   // reliable updates done
     int32_t restart_dir; // reliable updates restart the direction (p = r) instead of keeping it
+    int32_t xdefer;    // x += alpha p is applied by the next iteration's first MVM pass, not the update
+    int32_t xlag;      // (xdefer) x still lacks alpha p of the last step taken
 };
 
 // Refinement (outer) state, one per RHS.

@@ -36,6 +36,7 @@ struct PassArgs {
     const void* Ep;       // CG: p_old;  RESID / MATVEC: x
     const void* Er;       // CG: r;      RESID: b
     void* Epout;          // CG: p_new
+    void* Ex;             // CG: the iterate, when the first pass may apply x += alpha p_old (else null)
     const void* dvec;     // diagonal d (vector element type), may be null
     double sigma2;
 

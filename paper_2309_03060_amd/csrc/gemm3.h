@@ -16,6 +16,8 @@ struct Gemm3Args {
     const float* K1; const float* K2; const float* K3;
     const float* X;           // CG: p_old (p_new is written back in place); matvec: x
     const float* R;           // CG: r
+    float* Xit;               // CG with reliable updates: the iterate; the first pass applies the
+                              // previous step's x += alpha p_old (deferred from the update), else null
     float* Z1; float* Z2;     // intermediates, nrhs * n1 * n2 * n3 each
     float* Y;                 // q
     const float* dvec;        // n or null

@@ -74,6 +74,19 @@ __global__ __launch_bounds__(kThreads) void k_gemm3(Gemm3Args a, PassDesc d) {
     float* Pb = PNEW ? d.Pout + m0 * K : nullptr;
     const float* Bb = d.B + (int64_t)n0 * K;
     const double beta = PNEW ? a.cg[r].beta : 0.0;
+    // x += alpha p_old of the previous step, deferred from the vector update:
+    // this pass reads p_old anyway and is bound by its MFMAs, not its traffic
+    float* Xb = nullptr;
+    float xalpha = 0.f;
+    if constexpr (PNEW) {
+        if (a.Xit) {
+            if (threadIdx.x == 0) a.cg[r].xdefer = 1;      // every block stores the same value
+            if (a.cg[r].xlag) {
+                Xb = a.Xit + m0 * K;
+                xalpha = (float)a.cg[r].alpha;
+            }
+        }
+    }
     const uint32_t off = (uint32_t)(crow * K + ck);
 
     floatx16 acc[4][4];
@@ -82,13 +95,16 @@ __global__ __launch_bounds__(kThreads) void k_gemm3(Gemm3Args a, PassDesc d) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = floatx16{};
 
-    floatx4 ra[kChunks], rr[PNEW ? kChunks : 1], rb[kChunks];
+    floatx4 ra[kChunks], rr[PNEW ? kChunks : 1], rb[kChunks], rx[PNEW ? kChunks : 1];
     auto load = [&](int k0) {
 #pragma unroll
         for (int q = 0; q < kChunks; ++q) {
             const int64_t o = (int64_t)q * 32 * K + off + k0;
             ra[q] = *(const floatx4*)(Ab + o);
-            if constexpr (PNEW) rr[q] = *(const floatx4*)(Rb + o);
+            if constexpr (PNEW) {
+                rr[q] = *(const floatx4*)(Rb + o);
+                if (Xb) rx[q] = *(const floatx4*)(Xb + o);
+            }
             rb[q] = *(const floatx4*)(Bb + o);
         }
     };
@@ -101,6 +117,12 @@ __global__ __launch_bounds__(kThreads) void k_gemm3(Gemm3Args a, PassDesc d) {
         for (int q = 0; q < kChunks; ++q) {
             floatx4 v = ra[q];
             if constexpr (PNEW) {
+                if (Xb) {
+                    floatx4 xv = rx[q];
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) xv[c] = __builtin_fmaf(xalpha, v[c], xv[c]);
+                    *(floatx4*)(Xb + (int64_t)q * 32 * K + off + k0) = xv;
+                }
 #pragma unroll
                 for (int c = 0; c < 4; ++c) v[c] = pnew_of(rr[q][c], v[c], beta);
                 *(floatx4*)(Pb + (int64_t)q * 32 * K + off + k0) = v;
@@ -202,6 +224,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm3(Gemm3Args a, PassDesc d) {
         if (last_block_reduce(sum, a.partials + (int64_t)r * a.part_stride, a.counters + r, tpr, t, &tot, red) &&
             threadIdx.x == 0) {
             CgState& st = a.cg[r];
+            st.xlag = 0;                                   // the first pass has caught x up
             if (!(tot > 0.0) || !finite_d(tot)) {
                 st.status = finite_d(tot) ? COLA_ERR_NOT_SPD : COLA_ERR_NONFINITE;
                 st.active = 0;

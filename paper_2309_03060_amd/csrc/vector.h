@@ -21,7 +21,8 @@ hipError_t cg_prepare(const double* src, T* r, T* x, T* p, int64_t n, int nrhs, 
                       uint32_t* counters, SolveCounters* cnt, hipStream_t s);
 
 template <typename T>
-hipError_t reliable_fold(double* x64, T* xlo, int64_t n, int nrhs, const CgState* cg, bool all_rhs, hipStream_t s);
+hipError_t reliable_fold(double* x64, T* xlo, const T* p, int64_t n, int nrhs, const CgState* cg, bool all_rhs,
+                         hipStream_t s);
 
 template <typename T>
 hipError_t reliable_apply(const double* r64, T* rlo, int64_t n, int nrhs, CgState* cg, double* partials,

@@ -128,6 +128,8 @@ __global__ __launch_bounds__(kThreads) void k_cg_prepare(const double* src, T* r
         st.need_update = 0;
         st.fails = 0;
         st.updates = 0;
+        st.xdefer = 0;
+        st.xlag = 0;
         if (!finite_d(tot)) {
             st.status = COLA_ERR_NONFINITE;
             st.active = 0;
@@ -162,7 +164,20 @@ __global__ __launch_bounds__(kThreads) void k_cg_update(T* x, T* r, const T* p, 
     constexpr int W = Vec4<T>::W;
     const int64_t nv = (n % W == 0) ? n / W : 0;      // vector path when rows stay aligned
     const int64_t stride = (int64_t)gridDim.x * kThreads;
-    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < nv; i += stride) {
+    const bool defer = cg[g].xdefer != 0;               // x += alpha p left to the next first pass
+    if (defer) {
+        for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < nv; i += stride) {
+            VT rv = ((VT*)rg)[i];
+            const VT qv = ((const VT*)qg)[i];
+#pragma unroll
+            for (int c = 0; c < W; ++c) {
+                rv[c] = fmat(-alpha, qv[c], rv[c]);
+                s += (double)rv[c] * (double)rv[c];
+            }
+            ((VT*)rg)[i] = rv;
+        }
+    }
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; !defer && i < nv; i += stride) {
         VT xv = ((VT*)xg)[i], rv = ((VT*)rg)[i];
         const VT pv = ((const VT*)pg)[i], qv = ((const VT*)qg)[i];
 #pragma unroll
@@ -175,9 +190,8 @@ __global__ __launch_bounds__(kThreads) void k_cg_update(T* x, T* r, const T* p, 
         ((VT*)rg)[i] = rv;
     }
     for (int64_t i = nv * W + (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += stride) {
-        const T xv = fmat(alpha, pg[i], xg[i]);
         const T rv = fmat(-alpha, qg[i], rg[i]);
-        xg[i] = xv;
+        if (!defer) xg[i] = fmat(alpha, pg[i], xg[i]);
         rg[i] = rv;
         s += (double)rv * (double)rv;
     }
@@ -187,6 +201,7 @@ __global__ __launch_bounds__(kThreads) void k_cg_update(T* x, T* r, const T* p, 
         threadIdx.x == 0) {
         CgState& st = cg[g];
         st.iters += 1;
+        if (st.xdefer) st.xlag = 1;                      // x now lacks alpha p of this step
         if (hist && st.iters <= hist_len) {      // the CG coefficients behind the Lanczos tridiagonal
             double* h = hist + ((int64_t)g * hist_len + st.iters - 1) * 2;
             h[0] = st.alpha;
@@ -248,15 +263,21 @@ __global__ void k_outer_bookkeep(OuterState* outer, const CgState* cg, int nrhs,
 
 // Reliable update, step 1 (gated on need_update, or every RHS when
 // all_rhs): fold the low-precision iterate into the FP64 solution, x_lo = 0.
+// An iterate whose last step is still deferred (xlag) gets alpha p first, in
+// the working precision, as the vector update would have applied it.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_reliable_fold(double* x64, T* xlo, int64_t n, const CgState* cg,
-                                                            int all_rhs) {
+__global__ __launch_bounds__(kThreads) void k_reliable_fold(double* x64, T* xlo, const T* p, int64_t n,
+                                                            const CgState* cg, int all_rhs) {
     const int64_t g = blockIdx.y;
     if (!all_rhs && !cg[g].need_update) return;
     double* xg = x64 + g * n;
     T* lg = xlo + g * n;
+    const bool lag = p && cg[g].xlag;
+    const T alpha = (T)cg[g].alpha;
+    const T* pg = p ? p + g * n : nullptr;
     for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
-        xg[i] += (double)lg[i];
+        const T v = lag ? fmat(alpha, pg[i], lg[i]) : lg[i];
+        xg[i] += (double)v;
         lg[i] = (T)0;
     }
 }
@@ -279,6 +300,7 @@ __global__ __launch_bounds__(kThreads) void k_reliable_apply(const double* r64, 
     double tot;
     if (last_block_reduce(0.0, partials + g * part_stride, counters + g, gridDim.x, blockIdx.x, &tot, red) &&
         threadIdx.x == 0) {
+        cg[g].xlag = 0;                                  // the fold applied any deferred step
         reliable_finish(cg[g], cnt);
     }
 }
@@ -395,12 +417,14 @@ template hipError_t cg_prepare<double>(const double*, double*, double*, double*,
                                        hipStream_t);
 
 template <typename T>
-hipError_t reliable_fold(double* x64, T* xlo, int64_t n, int nrhs, const CgState* cg, bool all_rhs, hipStream_t s) {
+hipError_t reliable_fold(double* x64, T* xlo, const T* p, int64_t n, int nrhs, const CgState* cg, bool all_rhs,
+                         hipStream_t s) {
     dim3 grid(vec_blocks_per_rhs(n), nrhs);
-    hipLaunchKernelGGL(k_reliable_fold<T>, grid, dim3(kThreads), 0, s, x64, xlo, n, cg, all_rhs ? 1 : 0);
+    hipLaunchKernelGGL(k_reliable_fold<T>, grid, dim3(kThreads), 0, s, x64, xlo, p, n, cg, all_rhs ? 1 : 0);
     return hipGetLastError();
 }
-template hipError_t reliable_fold<float>(double*, float*, int64_t, int, const CgState*, bool, hipStream_t);
+template hipError_t reliable_fold<float>(double*, float*, const float*, int64_t, int, const CgState*, bool,
+                                         hipStream_t);
 
 template <typename T>
 hipError_t reliable_apply(const double* r64, T* rlo, int64_t n, int nrhs, CgState* cg, double* partials,
