@@ -122,6 +122,31 @@ def test_gemm3_deferred_iterate_at_iteration_limit(iters):
         assert abs(i["relres"] - r) <= 1e-3 * r + 1e-15
 
 
+@pytest.mark.parametrize("iters", [1, 5])
+def test_gemm2_deferred_iterate_at_iteration_limit(iters):
+    """The BF16 two-GEMM engine stopped at the iteration limit agrees with the BF16 contraction passes
+    to BF16 rounding (a dropped or doubled step would differ by O(1)), and its reported residual is
+    the oracle's FP64 residual of the returned X."""
+    from gpu_util import infos, make_op, pack, unpack
+    rng = np.random.default_rng(98)
+    s = wl.random_system(rng, (256, 512), nterms=2, diag=True, sigma2=0.3)
+    B = rng.standard_normal((3, s.n))
+    out = []
+    for gemm2 in (True, False):
+        op = make_op([s], prec="bf16")
+        op.set_engine("gemm2", gemm2)
+        X, info = op.solve(pack([B]), 3, tol=1e-12, max_iters=iters, prec="bf16", inner_tol=0.1)
+        out.append((unpack(X, [s], 3)[0], infos(info, 3)))
+        op.close()
+    (Xg, ig), (Xc, ic) = out
+    for i in ig + ic:
+        assert i["status"] == 1 and i["iters"] == iters, i
+    assert np.abs(Xg - Xc).max() <= 2e-2 * np.abs(Xc).max()
+    rr = kron.relres(s.factors, Xg, B, s.sigma2, s.diag)
+    for i, r in zip(ig, rr):
+        assert abs(i["relres"] - r) <= 1e-3 * r + 1e-15
+
+
 def test_refined_uneven_batch_fp32():
     w = wl.config3(nsys=6, dmin=5, dmax=40)
     (Xs), info = _solve(w.systems, w.B, "fp32", 1, tol=1e-8, max_iters=3000)
