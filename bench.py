@@ -875,7 +875,7 @@ def measured_traffic(workload, kernel, nrhs, rhs_iters, launches):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU (right-hand sides and systems would be split across GPUs without communication); --gpus must be 1"}))
         sys.exit(2)
     if args.pmc_summary:
         pmc_summary(args.pmc_summary, args.workload, args.pmc_out)
