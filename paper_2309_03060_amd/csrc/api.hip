@@ -223,9 +223,18 @@ int32_t enqueue_mvm(cola_op_s* op, const SysInfo& s, int prec, int nrhs, const v
         g.K1 = op->fac32 + s.fac_off[0];
         g.K2 = op->fac32 + s.fac_off[1];
         g.K3 = op->fac32 + s.fac_off[2];
+        if (prec == COLA_PREC_BF16X3) {      // the three BF16 planes of each factor
+            g.bf16x3 = 1;
+            g.K1b = op->facbf + s.fac_off[0];
+            g.K2b = op->facbf + s.fac_off[1];
+            g.K3b = op->facbf + s.fac_off[2];
+            g.plane = op->fac_elems;
+        }
         g.X = (const float*)X;
         g.R = (const float*)Rpnew;
-        g.Xit = tmpl.epi == EPI_CG ? (float*)tmpl.Ex : nullptr;
+        // the FP32 engine's direction pass also takes the deferred step x += alpha p_old; the BF16x3
+        // engine leaves x to the vector update
+        g.Xit = (tmpl.epi == EPI_CG && !g.bf16x3) ? (float*)tmpl.Ex : nullptr;
         g.Z1 = (float*)op->ws.inter[0];
         g.Z2 = (float*)op->ws.inter[1];
         g.Y = (float*)Yout;
@@ -241,8 +250,9 @@ int32_t enqueue_mvm(cola_op_s* op, const SysInfo& s, int prec, int nrhs, const v
         g.cnt = tmpl.cnt;
         auto al16 = [](const void* q) { return ((uintptr_t)q & 15) == 0; };
         const bool in_place_p = tmpl.epi != EPI_CG || tmpl.Epout == X;   // the direction is written over p_old
-        if (in_place_p && al16(g.K1) && al16(g.K2) && al16(g.K3) && al16(g.X) && al16(g.R) && al16(g.Y) &&
-            al16(g.dvec)) {
+        const bool planes_ok = !g.bf16x3 || (al16(g.K1b) && al16(g.K2b) && al16(g.K3b) && g.plane % 8 == 0);
+        if (in_place_p && planes_ok && al16(g.K1) && al16(g.K2) && al16(g.K3) && al16(g.X) && al16(g.R) &&
+            al16(g.Xit) && al16(g.Y) && al16(g.dvec)) {
             const char* names[3] = {"gemm_mode3", "gemm_mode2", "gemm_mode1"};
             for (int m = 3; m >= 1; --m) {
                 ProfScope ps(op->prof, names[3 - m], st);

@@ -125,6 +125,42 @@ __device__ inline bool last_block_reduce(double partial, double* partials, uint3
     return true;
 }
 
+// Block sum over the 8 waves of a GEMM block (fixed order); valid in every thread.
+__device__ inline double block_sum8(double v, double* smem8) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) smem8[wave] = v;
+    __syncthreads();
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < 8; ++w) t += smem8[w];
+    __syncthreads();
+    return t;
+}
+
+// The last-block-done reduction of common.h for 8-wave blocks.
+__device__ inline bool last_block_reduce8(double partial, double* partials, uint32_t* counter, int nblocks,
+                                          int myblock, double* total, double* smem8) {
+    __shared__ int s_last;
+    if (threadIdx.x == 0) {
+        store_coherent(&partials[myblock], partial);
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        __builtin_amdgcn_s_waitcnt(0);            // the partial store has completed
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        const uint32_t prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_last = (prev == (uint32_t)(nblocks - 1));
+    }
+    __syncthreads();
+    if (!s_last) return false;
+    double t = 0.0;
+    for (int i = threadIdx.x; i < nblocks; i += blockDim.x) t += load_coherent(&partials[i]);
+    t = block_sum8(t, smem8);
+    if (threadIdx.x == 0) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    *total = t;
+    return true;
+}
+
 // After a reliable update has put ||b - A x||^2 into st.rho_true (x already
 // holds the folded FP64 solution and r the replaced residual): decide
 // convergence from the true residual, resume a paused right-hand side, and

@@ -5,7 +5,7 @@
 namespace cola {
 
 // One term K1 (x) K2 (x) K3 (+ diagonal + sigma2 I), n1, n2 multiples of 256
-// and n3 = 256.  Each pass multiplies the last (contiguous) mode of its input
+// and n3 = 256, in FP32 or BF16x3 working precision.  Each pass multiplies the last (contiguous) mode of its input
 // by its factor and stores the result with the new mode first, so the next
 // pass again finds its mode contiguous:
 //   pass 3: Z1[r][c'][a][b] = sum_c  P[r][a][b][c]  K3[c', c]   (P = r + beta p_old when CG)
@@ -13,7 +13,10 @@ namespace cola {
 //   pass 1: q [r][a'][b'][c'] = sum_a Z2[r][b'][c'][a] K1[a', a] (+ diagonal; CG epilogue)
 struct Gemm3Args {
     int32_t n1, n2, n3, nrhs;
+    int32_t bf16x3;           // 0: FP32 factors K1..K3 on FP32 MFMA; 1: the BF16x3 splits K1b..K3b
     const float* K1; const float* K2; const float* K3;
+    const __bf16* K1b; const __bf16* K2b; const __bf16* K3b;   // BF16x3: hi plane of each factor
+    int64_t plane;            // BF16x3: elements between the hi, mid and lo planes
     const float* X;           // CG: p_old (p_new is written back in place); matvec: x
     const float* R;           // CG: r
     float* Xit;               // CG with reliable updates: the iterate; the first pass applies the

@@ -27,7 +27,7 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 // Sum over the 16 waves of an item's workgroup with a single barrier.  A
 // caller that sums again must use another slot array (or pass a barrier)
 // before it writes these slots again: other waves may still be reading them.
-__device__ inline double block_sum8(double v, double* smem) {
+__device__ inline double block_sum16(double v, double* smem) {
     v = wave_sum(v);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (lane == 0) smem[wave] = v;
@@ -244,7 +244,7 @@ __global__ __launch_bounds__(kResThreads) void k_resident_cg(ResArgs a) {
                     qo[j] = qv;
                     mu_l += (double)pe * (double)qv;
                 }
-            const double mu = block_sum8(mu_l, red_pq);
+            const double mu = block_sum16(mu_l, red_pq);
             if (!(mu > 0.0) || !finite_d(mu)) {
                 status = finite_d(mu) ? COLA_ERR_NOT_SPD : COLA_ERR_NONFINITE;
                 active = 0;
@@ -259,7 +259,7 @@ __global__ __launch_bounds__(kResThreads) void k_resident_cg(ResArgs a) {
                     rr[j] = __builtin_fmaf(-af, qo[j], rr[j]);
                     rho_l += (double)rr[j] * (double)rr[j];
                 }
-            const double rn = block_sum8(rho_l, red_rr);
+            const double rn = block_sum16(rho_l, red_rr);
             ++iters;
             bool stop = false;
             if (!finite_d(rn)) {
@@ -407,7 +407,7 @@ __global__ __launch_bounds__(kResidThreads) void k_resident_resid64(ResArgs a) {
                 }
             }
     }
-    rr = block_sum8(rr, red);
+    rr = block_sum16(rr, red);
     if (tid == 0) {
         st.rho_true = rr;
         if (!a.all_items) reliable_finish(st, a.cnt);

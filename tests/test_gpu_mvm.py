@@ -62,6 +62,51 @@ def test_matvec_low_precision(prec, tol, shape, nterms, diag):
     op.close()
 
 
+def _bf16_rounded_mvm(s, X):
+    """The oracle's product with every operand the BF16 path rounds rounded the same way (RNE via
+    FP32): the factors, x, and each intermediate before its mode is multiplied; modes are applied
+    last to first, as the passes do, and a single factor K acts as [1] (x) K (so its result is
+    rounded once more before the trivial first mode).  The diagonal term uses the FP32 x and d."""
+    dims = list(s.dims)
+    terms = s.factors
+    if len(dims) == 1:
+        dims = [1] + dims
+        terms = [[np.ones((1, 1))] + list(row) for row in terms]
+    Xr = lowprec.to_fp32(X)
+    Y = np.zeros_like(Xr)
+    for row in terms:
+        T = Xr
+        for k in reversed(range(len(dims))):
+            facs = [np.eye(d) for d in dims]
+            facs[k] = lowprec.to_bf16(row[k])
+            T = kron.kron_apply(facs, lowprec.to_bf16(T))
+        Y += T
+    dg = lowprec.to_fp32(np.full(s.n, s.sigma2) if s.diag is None else lowprec.to_fp32(s.diag) + s.sigma2)
+    return Y + dg[None, :] * Xr
+
+
+# BF16 against the oracle fed the same BF16 roundings: what remains is FP32 accumulation order and the
+# rare BF16 rounding of an intermediate that FP32 accumulation pushes across a tie (one BF16 ulp of one
+# element, ~2^-9 / n_k of the |K||x| scale).  Truncation instead of round-to-nearest-even, or a rounding
+# point lost or added, moves every entry by ~1e-4 .. 1e-3 of that scale.
+@pytest.mark.parametrize("shape,nterms,diag", SHAPES + [((256, 256), 1, False), ((256, 512), 3, True)])
+def test_matvec_bf16_against_rounded_oracle(shape, nterms, diag):
+    import torch
+    from gpu_util import make_op, pack, unpack
+    s = _systems(shape, nterms, diag, seed=1)
+    nrhs = 2
+    X = np.random.default_rng(2).standard_normal((nrhs, s.n))
+    op = make_op([s], prec="bf16")
+    Y = unpack(op.matvec(pack([X], torch.float32), nrhs), [s], nrhs)[0]
+    op.close()
+    ref = _bf16_rounded_mvm(s, X)
+    Xr = lowprec.to_fp32(X)
+    absref = kron.mvm([[np.abs(f) for f in row] for row in s.factors], np.abs(Xr), abs(s.sigma2),
+                      None if s.diag is None else np.abs(s.diag))
+    err = (np.abs(Y - ref) / absref).max()
+    assert err <= 3e-5, err
+
+
 def test_matvec_multi_system_packing():
     import torch
     from gpu_util import make_op, pack, unpack
@@ -147,21 +192,32 @@ def test_matvec_bf16_gemm_path_after_unaligned_system():
     op.close()
 
 
-# One-term three-mode operators with 256-wide modes run their FP32 MVM as three
-# dense GEMMs (each pass writes its output with the new mode first).
-@pytest.mark.parametrize("shape,diag,nrhs", [((256, 256, 256), True, 2), ((512, 256, 256), False, 1)])
-def test_matvec_fp32_dense_gemm3_path(shape, diag, nrhs):
+# One-term three-mode operators with 256-wide modes run their FP32 and BF16x3 MVMs as
+# three dense GEMMs (each pass writes its output with the new mode first); BF16x3
+# splits every operand three ways and sums six BF16 matrix-core products.
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("shape,diag,nrhs", [((256, 256, 256), True, 2), ((512, 256, 256), False, 1),
+                                             ((256, 512, 256), True, 3)])
+def test_matvec_dense_gemm3_path(shape, diag, nrhs, prec):
     import torch
     from gpu_util import make_op, pack, unpack
     s = _systems(shape, 1, diag, seed=7)
     X = np.random.default_rng(8).standard_normal((nrhs, s.n))
-    op = make_op([s], prec="fp32")
+    op = make_op([s], prec=prec)
     Y = unpack(op.matvec(pack([X], torch.float32), nrhs), [s], nrhs)[0]
     Xr = lowprec.to_fp32(X)
     ref = kron.mvm(s.factors, Xr, s.sigma2, s.diag)
     absref = kron.mvm([[np.abs(f) for f in row] for row in s.factors], np.abs(Xr), abs(s.sigma2),
                       None if s.diag is None else np.abs(s.diag))
-    # three FP32-accumulated contractions of length 256 and 512
+    # three FP32-accumulated contractions of length 256 and 512; for BF16x3 the dropped products
+    # (mid x lo, lo x mid, lo x lo) are about 2 * 2^-24 of each term.  A missing leading product
+    # (hh alone: ~2^-9; without hl / lh / mm: ~2^-17) fails this bound.
     err = (np.abs(Y - ref) / absref).max()
-    assert err <= 1e-5, err
+    assert err <= 2e-6, err
+    if prec == "bf16x3":
+        # the same splits through the general contraction passes (engine off): the same six
+        # products in another order, so the two agree to FP32 accumulation rounding
+        op.set_engine("gemm3", False)
+        Yc = unpack(op.matvec(pack([X], torch.float32), nrhs), [s], nrhs)[0]
+        assert (np.abs(Y - Yc) / absref).max() <= 2e-6
     op.close()

@@ -96,26 +96,31 @@ def test_refined_fp32_dense_gemm3_path():
         assert abs(i["relres"] - r) <= 1e-3 * r + 1e-15
 
 
-@pytest.mark.parametrize("iters", [1, 6])
-def test_gemm3_deferred_iterate_at_iteration_limit(iters):
-    """The three-GEMM engine applies x += alpha p one iteration late (in its first pass).  A solve
-    stopped by the iteration limit must still contain its last step: the same solve on the
-    contraction passes (x updated at once) agrees to FP32 rounding, while a dropped step would differ
-    by O(1); both are certified by the oracle's FP64 residual of the returned X."""
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("iters", [1, 6, 40])
+def test_gemm3_deferred_iterate_at_iteration_limit(iters, prec):
+    """The FP32 three-GEMM engine applies x += alpha p one iteration late (in its first pass).  A solve
+    stopped by the iteration limit must still contain its last step, also after reliable updates (the
+    fold catches a pending step up, the update clears the flag, the next iteration resumes the
+    deferral): the same solve on the contraction passes (x updated at once) agrees to FP32 rounding,
+    while a dropped or doubled step would differ by O(1); both are certified by the oracle's FP64
+    residual of the returned X.  The BF16x3 engine (x updated at once) is held to the same check."""
     from gpu_util import infos, make_op, pack, unpack
     rng = np.random.default_rng(97)
     s = wl.random_system(rng, (256, 256, 256), nterms=1, diag=False, sigma2=0.5)
     B = rng.standard_normal((2, s.n))
     out = []
     for gemm3 in (True, False):
-        op = make_op([s], prec="fp32")
+        op = make_op([s], prec=prec)
         op.set_engine("gemm3", gemm3)
-        X, info = op.solve(pack([B]), 2, tol=1e-12, max_iters=iters, prec="fp32", inner_tol=0.1)
+        X, info = op.solve(pack([B]), 2, tol=1e-12, max_iters=iters, prec=prec, inner_tol=0.1)
         out.append((unpack(X, [s], 2)[0], infos(info, 2)))
         op.close()
     (Xg, ig), (Xc, ic) = out
     for i in ig + ic:
         assert i["status"] == 1 and i["iters"] == iters, i
+        if iters >= 40:
+            assert i["sweeps"] >= 1, i                      # a reliable update was crossed (they fall at chunk ends)
     assert np.abs(Xg - Xc).max() <= 1e-4 * np.abs(Xc).max()
     rr = kron.relres(s.factors, Xg, B, s.sigma2)
     for i, r in zip(ig, rr):
