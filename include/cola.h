@@ -52,6 +52,7 @@ extern "C" {
 #define COLA_ERR_OOM          (-4)
 #define COLA_ERR_HIP          (-5)
 #define COLA_ERR_UNSUPPORTED  (-6)
+#define COLA_ERR_SCRATCH      (-7)  /* call too large for cola_kron_matvec_noalloc's static scratch */
 
 /* element types of caller vectors --------------------------------------- */
 #define COLA_F64 0
@@ -113,6 +114,25 @@ int32_t cola_op_size(cola_op_t op, int64_t* n_total, int32_t* nsys);
  * X and Y must not overlap. */
 int32_t cola_kron_matvec(cola_op_t op, const void* X, void* Y, int32_t nrhs,
                          int32_t dtype, int32_t prec, void* stream);
+
+/* Y = A X exactly as cola_kron_matvec, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  The pass intermediates live in a static device array
+ * of 64 MiB inside the library (two halves of 32 MiB) instead of the op's
+ * workspace, so the call allocates nothing (no hipMalloc, no workspace growth,
+ * no profiling events) and enqueues only kernels on `stream`.
+ *   Limit: (largest term count) * nrhs * (largest system's n) * (8 for
+ *   COLA_PREC_FP64, else 4) bytes must not exceed 32 MiB; larger calls return
+ *   COLA_ERR_SCRATCH and enqueue nothing.
+ *   The device that is current must be the op's device (else
+ *   COLA_ERR_INVALID_ARG).  Its first call on a device looks up that device's
+ *   copy of the array once (hipGetSymbolAddress).
+ *   Every call on one GPU shares that GPU's array, which keeps the last call's
+ *   contents (no call needs it cleared): calls that overlap on one GPU - two
+ *   streams, or two host threads - race and must be serialised by the caller.
+ * Arguments, layout and the other errors are those of cola_kron_matvec. */
+int32_t cola_kron_matvec_noalloc(cola_op_t op, const void* X, void* Y, int32_t nrhs, int32_t dtype,
+                                 int32_t prec, void* stream);
 
 /* mixed-precision scheme (cola_solve_opts.refine) ------------------------ */
 #define COLA_REFINE_RELIABLE 0  /* one low-precision CG; its residual is replaced by the FP64 true

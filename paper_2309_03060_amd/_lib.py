@@ -20,6 +20,7 @@ COLA_ERR_NONFINITE = -3
 COLA_ERR_OOM = -4
 COLA_ERR_HIP = -5
 COLA_ERR_UNSUPPORTED = -6
+COLA_ERR_SCRATCH = -7
 
 COLA_F64 = 0
 COLA_F32 = 1
@@ -41,6 +42,7 @@ PREC_BY_NAME = {"fp64": COLA_PREC_FP64, "fp32": COLA_PREC_FP32,
                 "bf16": COLA_PREC_BF16, "bf16x3": COLA_PREC_BF16X3}
 
 EXPORTED = ("cola_op_create", "cola_op_destroy", "cola_op_memory", "cola_op_size", "cola_kron_matvec",
+            "cola_kron_matvec_noalloc",
             "cola_op_diagonal", "cola_diag_estimate",
             "cola_cg_solve", "cola_cg_solve_backward", "cola_eig_solve", "cola_slq_logdet", "cola_autotune",
             "cola_op_set_engine", "cola_profile_enable", "cola_profile_read", "cola_status_string")
@@ -86,6 +88,7 @@ def lib():
         L.cola_op_memory.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), i32]
         L.cola_op_size.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i32)]
         L.cola_kron_matvec.argtypes = [vp, vp, vp, i32, i32, i32, vp]
+        L.cola_kron_matvec_noalloc.argtypes = [vp, vp, vp, i32, i32, i32, vp]
         L.cola_cg_solve.argtypes = [vp, vp, vp, i32, ctypes.POINTER(SolveOpts), vp, vp]
         L.cola_cg_solve_backward.argtypes = [vp, vp, vp, i32, ctypes.POINTER(SolveOpts), vp,
                                              ctypes.POINTER(vp), ctypes.POINTER(vp), vp, vp, vp]

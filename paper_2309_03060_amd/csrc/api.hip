@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "gemm.h"
@@ -141,9 +142,12 @@ TileCfg tile_for(const cola_op_s* op, int prec, bool rows, int64_t nk, int64_t B
 }
 
 struct ProfScope {
-    Profiler& p; const char* name; hipStream_t s;
-    ProfScope(Profiler& p_, const char* n, hipStream_t s_) : p(p_), name(n), s(s_) { if (p.enabled) p.begin(name, s); }
-    ~ProfScope() { if (p.enabled) p.end(name, s); }
+    Profiler* p; const char* name; hipStream_t s;
+    ProfScope(Profiler& p_, const char* n, hipStream_t s_) : p(&p_), name(n), s(s_) { if (p->enabled) p->begin(name, s); }
+    ProfScope(Profiler* p_, const char* n, hipStream_t s_) : p(p_), name(n), s(s_) {
+        if (p && p->enabled) p->begin(name, s);
+    }
+    ~ProfScope() { if (p && p->enabled) p->end(name, s); }
 };
 
 const void* fac_base(const cola_op_s* op, int prec) {
@@ -156,9 +160,12 @@ const void* fac_base(const cola_op_s* op, int prec) {
 
 // Enqueue the passes of one MVM of system `s` on nrhs packed vectors `X`.
 // The last pass (mode 1) applies epilogue `epi`; PassArgs fields for the
-// epilogue and gating are taken from `tmpl`.
+// epilogue and gating are taken from `tmpl`.  `inter` (two buffers of
+// Jmax * nrhs * nmax working-precision elements each) holds the pass
+// intermediates: the op's workspace, or the static scratch of the
+// no-allocation product; `prof` (or null) times the launches.
 int32_t enqueue_mvm(cola_op_s* op, const SysInfo& s, int prec, int nrhs, const void* X, const void* Rpnew,
-                    void* Yout, const PassArgs& tmpl, hipStream_t st) {
+                    void* Yout, const PassArgs& tmpl, hipStream_t st, void* const* inter, Profiler* prof) {
     const size_t esz = (prec == COLA_PREC_FP64) ? sizeof(double) : sizeof(float);
     const int64_t n = s.n;
     const int64_t tstride = (int64_t)nrhs * n;         // between per-term intermediates
@@ -181,8 +188,8 @@ int32_t enqueue_mvm(cola_op_s* op, const SysInfo& s, int prec, int nrhs, const v
         g.X = (const float*)X;
         g.R = (const float*)Rpnew;
         g.P = tmpl.epi == EPI_CG ? (float*)tmpl.Epout : nullptr;
-        g.P16 = (__bf16*)op->ws.inter[1];
-        g.T = (__bf16*)op->ws.inter[0];
+        g.P16 = (__bf16*)inter[1];
+        g.T = (__bf16*)inter[0];
         g.Y = (float*)Yout;
         g.dvec = (const float*)diag;
         g.sigma2 = s.sigma2;
@@ -197,15 +204,15 @@ int32_t enqueue_mvm(cola_op_s* op, const SysInfo& s, int prec, int nrhs, const v
         auto al16 = [](const void* q) { return ((uintptr_t)q & 15) == 0; };
         if (al16(g.U) && al16(g.V) && al16(g.X) && al16(g.R) && al16(g.P) && al16(g.Y) && al16(g.dvec)) {
             {
-                ProfScope ps(op->prof, "gemm_pack", st);
+                ProfScope ps(prof, "gemm_pack", st);
                 HIP_TRY(launch_gemm2(g, 0, st));
             }
             {
-                ProfScope ps(op->prof, "gemm_mode2", st);
+                ProfScope ps(prof, "gemm_mode2", st);
                 HIP_TRY(launch_gemm2(g, 1, st));
             }
             {
-                ProfScope ps(op->prof, "gemm_mode1", st);
+                ProfScope ps(prof, "gemm_mode1", st);
                 HIP_TRY(launch_gemm2(g, 2, st));
             }
             return COLA_OK;
@@ -235,8 +242,8 @@ int32_t enqueue_mvm(cola_op_s* op, const SysInfo& s, int prec, int nrhs, const v
         // the FP32 engine's direction pass also takes the deferred step x += alpha p_old; the BF16x3
         // engine leaves x to the vector update
         g.Xit = (tmpl.epi == EPI_CG && !g.bf16x3) ? (float*)tmpl.Ex : nullptr;
-        g.Z1 = (float*)op->ws.inter[0];
-        g.Z2 = (float*)op->ws.inter[1];
+        g.Z1 = (float*)inter[0];
+        g.Z2 = (float*)inter[1];
         g.Y = (float*)Yout;
         g.dvec = (const float*)diag;
         g.sigma2 = s.sigma2;
@@ -255,7 +262,7 @@ int32_t enqueue_mvm(cola_op_s* op, const SysInfo& s, int prec, int nrhs, const v
             al16(g.Xit) && al16(g.Y) && al16(g.dvec)) {
             const char* names[3] = {"gemm_mode3", "gemm_mode2", "gemm_mode1"};
             for (int m = 3; m >= 1; --m) {
-                ProfScope ps(op->prof, names[3 - m], st);
+                ProfScope ps(prof, names[3 - m], st);
                 HIP_TRY(launch_gemm3(g, m, st));
             }
             return COLA_OK;
@@ -278,7 +285,7 @@ int32_t enqueue_mvm(cola_op_s* op, const SysInfo& s, int prec, int nrhs, const v
         sa.pnew = Rpnew != nullptr;
         sa.X = X;
         sa.R = Rpnew;
-        sa.Y = op->ws.inter[0];
+        sa.Y = inter[0];
         sa.y_tstride = tstride;
         sa.K2 = (const char*)fac + (size_t)s.fac_off[1] * fb;
         sa.K3 = (const char*)fac + (size_t)s.fac_off[2] * fb;
@@ -288,10 +295,10 @@ int32_t enqueue_mvm(cola_op_s* op, const SysInfo& s, int prec, int nrhs, const v
         sa.gate_stride = tmpl.gate_stride;
         sa.cg = tmpl.cg;
         {
-            ProfScope ps(op->prof, prec == COLA_PREC_FP64 ? "slab23_fp64" : "slab23", st);
+            ProfScope ps(prof, prec == COLA_PREC_FP64 ? "slab23_fp64" : "slab23", st);
             HIP_TRY(launch_slab23(prec, sa, st));
         }
-        in = op->ws.inter[0];
+        in = inter[0];
         in_tstride = tstride;
         buf = 1;
         kstart = 0;
@@ -332,7 +339,7 @@ int32_t enqueue_mvm(cola_op_s* op, const SysInfo& s, int prec, int nrhs, const v
         } else {
             a.nsum = 1;
             a.nout = s.J;
-            a.Y = op->ws.inter[buf];
+            a.Y = inter[buf];
             a.y_tstride = tstride;
             a.epi = EPI_STORE;
             kname = prec == COLA_PREC_FP64 ? (rows ? "contract_rows_fp64" : "contract_mid_fp64")
@@ -340,7 +347,7 @@ int32_t enqueue_mvm(cola_op_s* op, const SysInfo& s, int prec, int nrhs, const v
         }
         TileCfg cfg = tile_for(op, prec, rows, nk, a.B, a.a_per_rhs);
         {
-            ProfScope ps(op->prof, kname, st);
+            ProfScope ps(prof, kname, st);
             HIP_TRY(launch_contract(prec, rows, a, cfg, st));
         }
         in = a.Y;
@@ -349,6 +356,11 @@ int32_t enqueue_mvm(cola_op_s* op, const SysInfo& s, int prec, int nrhs, const v
         (void)esz;
     }
     return COLA_OK;
+}
+
+int32_t enqueue_mvm(cola_op_s* op, const SysInfo& s, int prec, int nrhs, const void* X, const void* Rpnew,
+                    void* Yout, const PassArgs& tmpl, hipStream_t st) {
+    return enqueue_mvm(op, s, prec, nrhs, X, Rpnew, Yout, tmpl, st, op->ws.inter, &op->prof);
 }
 
 PassArgs base_args(cola_op_s* op) {
@@ -1067,6 +1079,36 @@ int32_t solve_small(cola_op_s* op, const double* B, double* X, int nrhs, const c
     return COLA_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Static scratch of the no-allocation product (cola_kron_matvec_noalloc): the two
+// pass intermediates live in this array instead of the op's workspace.  Each GPU
+// the library runs on holds its own copy from module load to process end.  In
+// host code `scratch` names a host-side stand-in, never device memory: its device
+// address comes from hipGetSymbolAddress, once per device, and only that address
+// is used (kernel arguments).
+constexpr size_t kScratchBytes = (size_t)64 << 20;   // two halves of 32 MiB
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of this device's scratch (device `dev` must be current).
+int32_t scratch_address(int dev, void** out) {
+    if (dev < 0 || dev >= kMaxDevices) return COLA_ERR_UNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return COLA_ERR_HIP;
+        }
+        g_scratch_dev[dev] = p;
+    }
+    *out = g_scratch_dev[dev];
+    return COLA_OK;
+}
+
 int32_t check_opts(const cola_op_s* op, const cola_solve_opts* o) {
     if (!o) return COLA_ERR_INVALID_ARG;
     if (!finite_pos(o->tol) || o->max_iters < 1 || o->check_every < 0) return COLA_ERR_INVALID_ARG;
@@ -1097,6 +1139,9 @@ const char* cola_status_string(int32_t status) {
         case COLA_ERR_OOM: return "device memory allocation failed";
         case COLA_ERR_HIP: return "HIP runtime error";
         case COLA_ERR_UNSUPPORTED: return "unsupported configuration";
+        case COLA_ERR_SCRATCH:
+            return "call too large for the static scratch of the no-allocation product (64 MiB: "
+                   "terms x nrhs x largest system x element size must not exceed 32 MiB)";
         default: return "unknown status";
     }
 }
@@ -1445,6 +1490,39 @@ int32_t cola_kron_matvec(cola_op_t op, const void* X, void* Y, int32_t nrhs, int
         a.epi = EPI_MATVEC;
         a.Ep = xs;
         rc = enqueue_mvm(op, s, prec, nrhs, xs, nullptr, ys, a, st);
+        if (rc != COLA_OK) return rc;
+    }
+    return COLA_OK;
+}
+
+int32_t cola_kron_matvec_noalloc(cola_op_t op, const void* X, void* Y, int32_t nrhs, int32_t dtype, int32_t prec,
+                                 void* stream) {
+    if (!op || !X || !Y || nrhs < 1) return COLA_ERR_INVALID_ARG;
+    if (prec == COLA_PREC_FP64) {
+        if (dtype != COLA_F64) return COLA_ERR_INVALID_ARG;
+    } else {
+        if (prec != op->prec || dtype != COLA_F32) return COLA_ERR_INVALID_ARG;
+    }
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return COLA_ERR_HIP;
+    if (dev != op->device) return COLA_ERR_INVALID_ARG;
+    const size_t esz = (dtype == COLA_F64) ? 8 : 4;
+    const size_t half = kScratchBytes / 2;
+    // each intermediate holds at most Jmax * nrhs * nmax elements of the working precision
+    if ((double)op->Jmax * (double)nrhs * (double)op->nmax * (double)esz > (double)half) return COLA_ERR_SCRATCH;
+    void* base = nullptr;
+    int32_t rc = scratch_address(dev, &base);
+    if (rc != COLA_OK) return rc;
+    void* const inter[2] = {base, (char*)base + half};
+    hipStream_t st = S(stream);
+    for (const SysInfo& s : op->sys) {
+        const char* xs = (const char*)X + esz * (size_t)nrhs * s.vec_off;
+        char* ys = (char*)Y + esz * (size_t)nrhs * s.vec_off;
+        PassArgs a;
+        std::memset(&a, 0, sizeof(a));                  // a product needs no reduction buffers
+        a.epi = EPI_MATVEC;
+        a.Ep = xs;
+        rc = enqueue_mvm(op, s, prec, nrhs, xs, nullptr, ys, a, st, inter, nullptr);
         if (rc != COLA_OK) return rc;
     }
     return COLA_OK;

@@ -119,6 +119,19 @@ class KronOperator:
                                                               dtype, p, _stream_ptr()))
         return Y
 
+    def matvec_noalloc(self, X: torch.Tensor, Y: torch.Tensor, nrhs: int, prec: Optional[str] = None) -> torch.Tensor:
+        """Y = A X into the caller's Y (cola_kron_matvec_noalloc): no device memory is allocated by
+        the library or here; the intermediates use the library's static scratch (see cola.h)."""
+        p = self.prec if prec is None else L.PREC_BY_NAME[prec]
+        dtype = L.COLA_F64 if p == L.COLA_PREC_FP64 else L.COLA_F32
+        tdt = torch.float64 if dtype == L.COLA_F64 else torch.float32
+        for t in (X, Y):
+            if t.dtype != tdt or not t.is_contiguous():
+                raise ValueError(f"X and Y must be contiguous {tdt} device tensors")
+        L.check("cola_kron_matvec_noalloc", self.lib.cola_kron_matvec_noalloc(
+            self.handle, X.data_ptr(), Y.data_ptr(), nrhs, dtype, p, _stream_ptr()))
+        return Y
+
     def _opts(self, tol, max_iters, prec, inner_tol, max_sweeps, check_every, refine="reliable",
               precond="none") -> L.SolveOpts:
         o = L.SolveOpts()

@@ -43,6 +43,8 @@ def test_status_strings_and_null_argument_errors():
     assert lib.cola_op_create(None, 1, 0, None, None) == L.COLA_ERR_INVALID_ARG
     assert lib.cola_op_destroy(None) == L.COLA_OK
     assert lib.cola_kron_matvec(None, None, None, 1, 0, 0, None) == L.COLA_ERR_INVALID_ARG
+    assert lib.cola_kron_matvec_noalloc(None, None, None, 1, 0, 0, None) == L.COLA_ERR_INVALID_ARG
+    assert "scratch" in L.status_string(L.COLA_ERR_SCRATCH)
     assert lib.cola_cg_solve(None, None, None, 1, None, None, None) == L.COLA_ERR_INVALID_ARG
     assert lib.cola_cg_solve_backward(None, None, None, 1, None, None, None, None, None, None, None) == \
         L.COLA_ERR_INVALID_ARG
