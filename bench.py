@@ -586,6 +586,36 @@ MFMA_PEAK_TFLOPS = {"fp32": FP32_MFMA_PEAK_TFLOPS, "bf16": 2500.0, "bf16x3": 250
 PRODUCTS_PER_FLOP = {"fp32": 1, "bf16": 1, "bf16x3": 6, "fp64": 1}
 
 
+def class_model(cls, prec, n, dims, J, has_diag, deferral):
+    """(algorithmic FLOPs, algorithmic HBM bytes) per right-hand-side iteration of one launch class of the
+    low-precision MVM and CG update (FP32 working vectors: 4 bytes a word), or None for other classes.
+
+    Three-GEMM passes (one term, three 256-wide modes): the direction pass reads r and p_old and writes p
+    and its output (16 B; +8 B when it also takes x += alpha p); the middle pass reads and writes one
+    intermediate (8 B); the last pass reads the intermediate and p and writes q (12 B, +4 B for a
+    diagonal).  Two-GEMM passes (BF16, J terms): the pack reads r, p_old and writes p and its BF16 copy
+    (14 B); mode 2 reads the BF16 copy and writes J BF16 intermediates; mode 1 reads them, p (and d) and
+    writes q.  The vector update reads x, r, p, q and writes x, r (24 B; 12 B when x is left to the
+    direction pass).  FLOPs are the mode's Table 2 contraction cost times the matrix-core products per
+    useful product."""
+    prod = PRODUCTS_PER_FLOP[prec]
+    F = len(dims)
+    if cls == "update":
+        return 6.0 * n, (12.0 if deferral else 24.0) * n
+    if F == 3 and J == 1 and cls.startswith("gemm_mode"):
+        m = int(cls[-1])
+        fl = 2.0 * n * dims[m - 1] * prod
+        by = {3: 16.0 + (8.0 if deferral else 0.0), 2: 8.0, 1: 12.0 + (4.0 if has_diag else 0.0)}[m]
+        return fl, by * n
+    if F == 2 and cls == "gemm_pack":
+        return 2.0 * n, 14.0 * n
+    if F == 2 and cls == "gemm_mode2":
+        return 2.0 * n * dims[1] * J * prod, (2.0 + 2.0 * J) * n
+    if F == 2 and cls == "gemm_mode1":
+        return 2.0 * n * dims[0] * J * prod, (2.0 * J + 8.0 + (4.0 if has_diag else 0.0)) * n
+    return None
+
+
 def run_single(args, name):
     """Large single-system workloads: 256^3 x 8 RHS (windows of CG iterations), the sum of 4 1024^2
     terms + diag (solve + backward per step), or the 64^2 FP64 system (one solve per step)."""
@@ -637,39 +667,57 @@ def run_single(args, name):
     # algorithmic FLOPs of one RHS*iteration of the working-precision MVM (Table 2 cost, per mode),
     # times the matrix-core products the working precision prescribes per useful product
     flop_rhs_it = 2.0 * n * J * sum(dims) * prod
-    # modes contracted by each launch class (1-based, mode 1 = leading)
-    F = len(dims)
-    modes_of = {"slab23": [2, 3], "contract_rows": [F], "contract_mid": [2], "contract_last": [1],
-                "gemm_mode3": [3], "gemm_mode2": [2], "gemm_mode1": [1]}
-    per_kernel = {k: {"avg_us": round(v["avg_us"], 2), "launches": v["launches"]} for k, v in kern.items()}
-    mvm = {k: v for k, v in kern.items() if k.replace("_fp64", "") in modes_of}
-    contract_ms = sum(v["total_ms"] for k, v in kern.items() if not k.startswith("update"))
+    # the FP32 three-GEMM engine takes x += alpha p in its direction pass (reliable-update solves)
+    deferral = prec == "fp32" and name == "c4"
+    models = {k: class_model(k, prec, n, dims, J, s.diag is not None, deferral) for k in kern}
+    models = {k: m for k, m in models.items() if m is not None}
+    per_kernel = {}
+    for k, v in kern.items():
+        per_kernel[k] = {"avg_us": round(v["avg_us"], 2), "launches": v["launches"],
+                         "share_of_kernel_time": round(v["total_ms"] / sum(u["total_ms"] for u in kern.values()), 4)}
+        if k in models:
+            fl, by = models[k]
+            t = v["total_ms"] * 1e-3
+            per_kernel[k]["GB/s"] = round(by * rhs_iters / t / 1e9, 1)
+            per_kernel[k]["TFLOP/s"] = round(fl * rhs_iters / t / 1e12, 2)
+            per_kernel[k]["alg_bytes_per_elem"] = by / n
     roof = None
-    if mvm:
-        peak = MFMA_PEAK_TFLOPS[prec]
-        dom = max(mvm, key=lambda k: mvm[k]["total_ms"])
-        v = mvm[dom]
+    if models:
+        peak_tf = MFMA_PEAK_TFLOPS[prec]
+        ridge = peak_tf * 1e12 / (HBM_PEAK_GBS * 1e9)          # FLOP per byte where the two bounds meet
+        dom = max(models, key=lambda k: kern[k]["total_ms"])
+        v = kern[dom]
+        fl, by = models[dom]
         # one launch processes every active RHS once; summed over launches that is rhs_iters
-        flop_launch = 2.0 * n * J * sum(dims[m - 1] for m in modes_of[dom.replace("_fp64", "")]) * prod * rhs_iters \
-            / v["launches"]
-        ach = flop_launch / (v["avg_us"] * 1e-6) / 1e12
-        agg = flop_rhs_it * rhs_iters / (contract_ms * 1e-3) / 1e12
-        roof = {"kernel": dom, "bound": "mfma", "achieved": round(ach, 2), "peak": peak, "unit": "TFLOP/s",
-                "frac": round(ach / peak, 4), "traffic": None, "flops_per_launch": round(flop_launch),
+        fl_launch = fl * rhs_iters / v["launches"]
+        by_launch = by * rhs_iters / v["launches"]
+        sec = v["avg_us"] * 1e-6
+        hbm = {"achieved": round(by_launch / sec / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+               "frac": round(by_launch / sec / 1e9 / HBM_PEAK_GBS, 4), "bytes_per_launch": round(by_launch)}
+        mf = {"achieved": round(fl_launch / sec / 1e12, 2), "peak": peak_tf, "unit": "TFLOP/s",
+              "frac": round(fl_launch / sec / 1e12 / peak_tf, 4), "flops_per_launch": round(fl_launch)}
+        bound = "mfma" if fl / by >= ridge else "hbm"
+        main, other = (mf, hbm) if bound == "mfma" else (hbm, mf)
+        roof = {"kernel": dom, "bound": bound, "achieved": main["achieved"], "peak": main["peak"],
+                "unit": main["unit"], "frac": main["frac"], "traffic": None,
+                "arithmetic_intensity": round(fl / by, 2), "ridge": round(ridge, 1),
                 "avg_launch_us": round(v["avg_us"], 2), "launches": v["launches"],
-                "all_mvm_passes": {"achieved": round(agg, 2), "frac": round(agg / peak, 4),
-                                   "note": "every MVM launch class of the working precision (operand packing "
-                                           "included) against the same peak"},
-                "per_kernel": per_kernel,
-                "fp64_residual_passes": {k: {"avg_us": round(v["avg_us"], 2), "launches": v["launches"]}
-                                         for k, v in resid64.items()}}
+                "other_bound": other, "per_kernel": per_kernel,
+                "fp64_residual_passes": {k: {"avg_us": round(u["avg_us"], 2), "launches": u["launches"]}
+                                         for k, u in resid64.items()}}
+        roof.update({k: main[k] for k in ("bytes_per_launch", "flops_per_launch") if k in main})
+        mvm_ms = sum(u["total_ms"] for k, u in kern.items() if k.startswith("gemm") or k.startswith("contract")
+                     or k.startswith("slab"))
+        if mvm_ms > 0:
+            agg = flop_rhs_it * rhs_iters / (mvm_ms * 1e-3) / 1e12
+            roof["all_mvm_passes"] = {"achieved": round(agg, 2), "unit": "TFLOP/s", "frac": round(agg / peak_tf, 4),
+                                      "note": "every MVM launch class of the working precision (operand packing "
+                                              "included) against the matrix-core peak"}
         if prod > 1:
-            roof["fp32_equivalent_TFLOPs"] = round(ach / prod, 2)
             roof["note"] = (f"{prec} issues {prod} bf16 matrix-core products per useful product (hh, hm, mh, hl, "
-                            f"lh, mm of the three-way splits); achieved counts all of them, against the bf16 peak")
-        if name == "c4":
-            tr = measured_traffic("c4", dom, nrhs, rhs_iters, v["launches"])
-            roof["traffic"] = tr
+                            f"lh, mm of the three-way splits); FLOP figures count all of them, against the bf16 "
+                            f"peak")
+        roof["traffic"] = measured_traffic(name, dom, nrhs, rhs_iters, v["launches"])
     elif "small_cg64" in kern:
         # the whole FP64 solve of each (system, RHS) in one workgroup: one launch per solve
         v = kern["small_cg64"]
@@ -832,22 +880,36 @@ KERNEL_SOURCES = {                   # files each launch class is compiled from 
     "slab23": ["slab.hip", "slab.h", "common.h"],
     "update": ["vector.hip", "vector.h", "common.h"],
     "cg_fused": ["fused.hip", "fused.h", "common.h"],
+    "gemm3": ["gemm3.hip", "gemm3.h", "common.h"],
+    "gemm2": ["gemm.hip", "gemm.h", "common.h"],
 }
 # bench launch-class name of each counter class, per workload (c2 fuses modes 2 and 3 in the slab pass,
 # so its only column-layout FP32 contraction is the last mode; the fused persistent CG replaces all three)
 BENCH_CLASS = {"c2": {"contract_cols_f32": "contract_last", "slab23_f32": "slab23", "update_float": "update",
-                      "k_fused_cg": "cg_fused"}}
+                      "k_fused_cg": "cg_fused"},
+               "c4": {"gemm3x3_mode3": "gemm_mode3", "gemm3x3_mode2": "gemm_mode2", "gemm3x3_mode1": "gemm_mode1",
+                      "gemm3_mode3": "gemm_mode3", "gemm3_mode2": "gemm_mode2", "gemm3_mode1": "gemm_mode1",
+                      "update_float": "update"},
+               "c5": {"k_gemm2_pack": "gemm_pack", "k_gemm2_t": "gemm_mode2", "k_gemm2_y": "gemm_mode1",
+                      "update_float": "update"}}
 # RHS*iterations one dispatch of a counter class covers in the counters run (default: one iteration of
 # every right-hand side)
 RHS_ITERS_PER_DISPATCH = {("c2", "k_fused_cg"): COUNTERS_C2_ITERS * 32}
 
 
-def source_kind(cls):
-    """KERNEL_SOURCES key of a counter or bench launch class."""
+def source_kind(cls, workload=None):
+    """KERNEL_SOURCES key of a counter or bench launch class (the bench's GEMM class names are shared by
+    the three-GEMM engine of the 256^3 workload and the two-GEMM engine of the sum-of-Kronecker one)."""
     if cls.startswith("contract"):
         return "contract"
     if cls in ("k_fused_cg", "cg_fused"):
         return "cg_fused"
+    if cls.startswith("gemm3"):
+        return "gemm3"
+    if cls.startswith("k_gemm2"):
+        return "gemm2"
+    if cls.startswith("gemm_"):
+        return "gemm2" if workload == "c5" else "gemm3"
     return cls.split("_")[0]
 
 
@@ -863,6 +925,10 @@ def kernel_class(name):
     m = re.search(r"k_cg_update<(\w+)", name)
     if m:
         return f"update_{m.group(1)}"
+    m = re.search(r"k_gemm3(x3)?<(true|false), (\d+)>", name)
+    if m:                                # the direction pass, the middle pass, the pass with the epilogue
+        mode = 3 if m.group(2) == "true" else (2 if m.group(3) == "0" else 1)
+        return f"gemm3{m.group(1) or ''}_mode{mode}"
     m = re.search(r"cola::(?:\(anonymous namespace\)::)?(k_\w+)", name)
     return m.group(1) if m else "other"
 
@@ -972,7 +1038,7 @@ def measured_traffic(workload, kernel, nrhs, rhs_iters, launches):
         rec = json.load(open(PMC_FILE))[workload]["kernels"][kernel]
     except (OSError, KeyError, ValueError):
         return None
-    if rec.get("sources_sha1") != sources_digest(source_kind(kernel)):
+    if rec.get("sources_sha1") != sources_digest(source_kind(kernel, workload)):
         return None
     per_rhs_iter = rec["bytes_per_launch_all_rhs_active"] / rec.get("rhs_iters_per_dispatch", nrhs)
     return int(per_rhs_iter * rhs_iters / launches)
