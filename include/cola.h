@@ -168,6 +168,18 @@ typedef struct {
                              plain CG does; the first call sets M up (Jacobi: one pass
                              over the diagonal rules; Kronecker-eigen: the first term's
                              factor eigendecompositions, waiting on the stream). */
+    int32_t x0_given;     /* 0: x0 = 0.  != 0: X holds the initial iterate on entry (warm
+                             start, e.g. resuming a solve stopped by max_iters from its X):
+                             CG starts from r0 = b - A x0 formed with the FP64 factors, and
+                             tolerances stay relative to ||b||                          */
+    int32_t hist_stride;  /* > 0 with hist: record the recursive relative residual
+                             ||r_k|| / ||b|| after every hist_stride-th iteration (the
+                             residual against MVM count of the paper's convergence plots) */
+    int32_t hist_len;     /* entries per right-hand side in hist                          */
+    int32_t reserved;
+    double* hist;         /* NULL, or DEVICE nsys*nrhs*hist_len doubles, row (system, RHS)
+                             in packing order, entry k after iteration (k+1)*hist_stride;
+                             the call first fills every entry with NaN                    */
 } cola_solve_opts;
 
 /* Per (system, RHS) outcome, written to DEVICE memory in stream order. */
@@ -177,13 +189,17 @@ typedef struct {
     int32_t iters;        /* CG iterations summed over all sweeps               */
     int32_t sweeps;       /* refinement sweeps or reliable updates (0 for a plain solve) */
     int32_t reserved;
-    double  relres;       /* final relative residual: the FP64 true residual
-                             when refining, the recursive one for a plain solve */
+    double  relres_recursive; /* ||r|| / ||b|| of the CG recurrence at its end (restarted
+                                 refinement: its FP64 residual)                        */
+    double  relres_true;  /* ||b - A x|| / ||b|| of the returned x with the FP64 factors
+                             (absolute residuals for b = 0).  Plain FP64 solves stop on
+                             the recursive residual; mixed-precision solves on this one  */
 } cola_solve_info;
 
 /* Solve A X = B for nrhs right-hand sides (packed, float64, device).
  *  - prec == COLA_PREC_FP64: textbook CG in FP64 to tol on the recursive
- *    residual, x0 = 0.
+ *    residual, from x0 = 0 or the caller's X (x0_given); one FP64 product of
+ *    the returned X gives relres_true.
  *  - prec == the op's working precision: mixed precision with an FP64
  *    residual formed from the FP64 factors, stopping when the FP64 relative
  *    residual <= tol.  refine == COLA_REFINE_RELIABLE (default): a single CG in
@@ -195,6 +211,10 @@ typedef struct {
  * Right-hand sides converge independently; the call ends when all have
  * converged or hit a limit (the multi-RHS semantics of the paper's block
  * solves, App. D.5).  info: device array of nsys*nrhs entries, or NULL.
+ * A warm start or a residual history takes the general multi-kernel path for
+ * ops of many small systems (the resident batched kernel starts from zero and
+ * records no history) and the separate-kernel path for the persistent fused CG
+ * when a history is asked for.
  * The first call for a given nrhs allocates workspace (not capture-safe);
  * later calls with nrhs no larger allocate nothing. */
 int32_t cola_cg_solve(cola_op_t op, const double* B, double* X, int32_t nrhs,
@@ -229,9 +249,8 @@ int32_t cola_cg_solve_backward(cola_op_t op, const double* X, const double* G, i
  * device forms est = ||z||^2 e1^T log(T) e1 by Gauss quadrature and
  * logdet = mean of est.
  *   X:      NULL, or device FP64 (packed like Z) receiving A^{-1} Z (the
- *           Hutchinson estimate of d log det / d theta is mean_z
- *           (A^{-1} z)^T (dA/dtheta) z: cola_cg_solve_backward with X = G = Z
- *           returns it times -nprobes);
+ *           gradient of log det from the same probes is cola_logdet_grad,
+ *           which can warm-start from this X);
  *   logdet: device array of nsys doubles;
  *   est:    NULL, or device array of nsys * nprobes per-probe estimates (NaN
  *           for a probe whose CG broke down);
@@ -241,6 +260,19 @@ int32_t cola_cg_solve_backward(cola_op_t op, const double* X, const double* G, i
  * max_iters allocates workspace. */
 int32_t cola_slq_logdet(cola_op_t op, const double* Z, int32_t nprobes, double tol, int32_t max_iters,
                         double* X, double* logdet, double* est, cola_solve_info* info, void* stream);
+
+/* Gradient of log det A per system (App. A: log det A = Tr(Log(A)); its derivative
+ * Tr(A^{-1} dA/dtheta), estimated with probes as in Sec. 4's GP training): the
+ * Hutchinson estimate (1/N) sum_z (A^{-1} z)^T (dA/dtheta) z over the N = nprobes
+ * probe vectors Z (packed like B of cola_cg_solve, e.g. Rademacher), i.e. the solve
+ * VJP of App. B.2 with X = G = Z, negated and divided by N inside the library.
+ *   Lambda:   device FP64 like Z, receives A^{-1} Z (an ordinary cola_cg_solve with
+ *             opts, which may warm-start from it, e.g. with the X of cola_slq_logdet);
+ *   dfactors, ddiag, dsigma2, info: as for cola_cg_solve_backward.
+ * Enqueued on `stream`; the first call for a given nprobes allocates workspace. */
+int32_t cola_logdet_grad(cola_op_t op, const double* Z, int32_t nprobes, const cola_solve_opts* opts,
+                         double* Lambda, void* const* dfactors, void* const* ddiag, double* dsigma2,
+                         cola_solve_info* info, void* stream);
 
 /* Diag(A) of every system, exactly: Diag(A + B) = Diag(A) + Diag(B) and
  * Diag(A (x) B) = vec(Diag(A) Diag(B)^T) (App. A, diagonal rules; row-major

@@ -44,7 +44,8 @@ PREC_BY_NAME = {"fp64": COLA_PREC_FP64, "fp32": COLA_PREC_FP32,
 EXPORTED = ("cola_op_create", "cola_op_destroy", "cola_op_memory", "cola_op_size", "cola_kron_matvec",
             "cola_kron_matvec_noalloc",
             "cola_op_diagonal", "cola_diag_estimate",
-            "cola_cg_solve", "cola_cg_solve_backward", "cola_eig_solve", "cola_slq_logdet", "cola_autotune",
+            "cola_cg_solve", "cola_cg_solve_backward", "cola_logdet_grad", "cola_eig_solve", "cola_slq_logdet",
+            "cola_autotune",
             "cola_op_set_engine", "cola_profile_enable", "cola_profile_read", "cola_status_string")
 
 
@@ -57,12 +58,18 @@ class SystemDesc(ctypes.Structure):
 class SolveOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iters", ctypes.c_int32), ("prec", ctypes.c_int32),
                 ("inner_tol", ctypes.c_double), ("max_sweeps", ctypes.c_int32),
-                ("check_every", ctypes.c_int32), ("refine", ctypes.c_int32), ("precond", ctypes.c_int32)]
+                ("check_every", ctypes.c_int32), ("refine", ctypes.c_int32), ("precond", ctypes.c_int32),
+                ("x0_given", ctypes.c_int32), ("hist_stride", ctypes.c_int32), ("hist_len", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("hist", ctypes.c_void_p)]
 
 
 class SolveInfo(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32), ("sweeps", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("relres", ctypes.c_double)]
+                ("reserved", ctypes.c_int32), ("relres_recursive", ctypes.c_double),
+                ("relres_true", ctypes.c_double)]
+
+
+INFO_WORDS = ctypes.sizeof(SolveInfo) // 4      # int32 words per cola_solve_info record
 
 
 class ColaError(RuntimeError):
@@ -92,6 +99,8 @@ def lib():
         L.cola_cg_solve.argtypes = [vp, vp, vp, i32, ctypes.POINTER(SolveOpts), vp, vp]
         L.cola_cg_solve_backward.argtypes = [vp, vp, vp, i32, ctypes.POINTER(SolveOpts), vp,
                                              ctypes.POINTER(vp), ctypes.POINTER(vp), vp, vp, vp]
+        L.cola_logdet_grad.argtypes = [vp, vp, i32, ctypes.POINTER(SolveOpts), vp, ctypes.POINTER(vp),
+                                       ctypes.POINTER(vp), vp, vp, vp]
         L.cola_eig_solve.argtypes = [vp, vp, vp, i32, vp]
         L.cola_op_diagonal.argtypes = [vp, vp, vp]
         L.cola_diag_estimate.argtypes = [vp, vp, i32, i32, vp, vp]

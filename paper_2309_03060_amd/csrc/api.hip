@@ -402,7 +402,7 @@ int32_t enqueue_iteration(cola_op_s* op, const SysInfo& s, int prec, int nrhs, T
     if (rc != COLA_OK) return rc;
     ProfScope ps(op->prof, sizeof(T) == 8 ? "update_fp64" : "update", st);
     HIP_TRY(cg_update<T>(x, r, p, q, s.n, nrhs, w.cg, w.partials, (int)w.part_stride, w.counters, w.cnt, st,
-                         sizeof(T) == 8 ? w.hist : nullptr, w.hist_len));
+                         sizeof(T) == 8 ? w.hist : nullptr, w.hist_len, w.rh));
     return COLA_OK;
 }
 
@@ -510,7 +510,8 @@ int32_t ensure_fused(cola_op_s* op) {
 }
 
 bool fused_eligible(const cola_op_s* op, const SysInfo& s, int prec, int check_every) {
-    return op->use_fused && check_every > 0 && op->fused_max_blocks != 0 && prec == op->prec &&
+    // the persistent kernel runs its own vector update, which records no residual history
+    return op->use_fused && check_every > 0 && op->fused_max_blocks != 0 && prec == op->prec && !op->ws.rh.data &&
            fused_cg_supported(prec, s.Fv, s.J, s.dims);
 }
 
@@ -620,7 +621,7 @@ int32_t run_cg(cola_op_s* op, const SysInfo& s, int prec, int nrhs, T* x, T* r, 
     GraphSet* gs = nullptr;
     if (op->graphs_ok) {
         GraphKey key{&s, prec, nrhs, x, r, p, q, chunk, (op->prof.enabled ? 1 : 0) + (tail ? 2 : 0),
-                     op->tiles_version, sizeof(T) == 8 ? w.hist : nullptr};
+                     op->tiles_version, sizeof(T) == 8 ? w.hist : nullptr, w.rh.data, w.rh.stride, w.rh.len};
         auto it = op->graphs.find(key);
         if (it == op->graphs.end() && op->graphs.size() >= 32) destroy_graphs(op);   // keep the cache bounded
         if (it == op->graphs.end()) {
@@ -768,6 +769,28 @@ int32_t apply_kron_eig(cola_op_s* op, size_t si, int nrhs, const double* r, doub
     return COLA_OK;
 }
 
+// r64 = B - A x with the FP64 factors for every right-hand side, ||r64||^2 into cg.rho_true.
+int32_t true_residual(cola_op_s* op, const SysInfo& s, const double* B, const double* x, int nrhs,
+                      hipStream_t st) {
+    Workspace& w = op->ws;
+    PassArgs a = base_args(op);
+    a.cg = w.cg;
+    a.epi = EPI_RESID_CG;
+    a.Ep = x;
+    a.Er = B;
+    return enqueue_mvm(op, s, COLA_PREC_FP64, nrhs, x, nullptr, w.r64, a, st);
+}
+
+// Warm start of an FP64 CG: x = x0 (the caller's X), r0 = B - A x0 in r64, ||B||^2 in cg.bnorm2;
+// cg_prepare then starts from src = r64 keeping x and the norm.
+int32_t warm_start64(cola_op_s* op, const SysInfo& s, const double* B, const double* X0, double* x, int nrhs,
+                     hipStream_t st) {
+    Workspace& w = op->ws;
+    HIP_TRY(copy_f64(X0, x, (int64_t)nrhs * s.n, st));
+    HIP_TRY(rhs_norm2(B, s.n, nrhs, w.cg, w.partials, (int)w.part_stride, w.counters, st));
+    return true_residual(op, s, B, x, nrhs, st);
+}
+
 // Preconditioned CG in FP64 (textbook recurrence): the MVM pass forms
 // p = z + beta p and the step length as in plain CG, the update kernel moves x
 // and r and decides convergence on ||r||, then z = M^{-1} r and r.z give the
@@ -802,8 +825,13 @@ int32_t run_pcg(cola_op_s* op, const SysInfo& s, const double* B, double* X, int
         return COLA_OK;
     };
     HIP_TRY(fill_i32(&w.cnt->num_active, 0, 1, st));
-    HIP_TRY(cg_prepare<double>(B, r, x, p, n, nrhs, nullptr, w.cg, o->tol, o->max_iters, 0.0, w.partials, ps,
-                               w.counters, w.cnt, st));
+    const bool warm = o->x0_given && X;
+    if (warm) {
+        rc = warm_start64(op, s, B, X, x, nrhs, st);      // r0 in r64, which z reuses after the prepare
+        if (rc != COLA_OK) return rc;
+    }
+    HIP_TRY(cg_prepare<double>(warm ? w.r64 : B, r, x, p, n, nrhs, nullptr, w.cg, o->tol, o->max_iters, 0.0,
+                               w.partials, ps, w.counters, w.cnt, st, warm, warm));
     rc = precondition();
     if (rc != COLA_OK) return rc;
     for (int it = 0; it < o->max_iters; ++it) {
@@ -825,12 +853,14 @@ int32_t run_pcg(cola_op_s* op, const SysInfo& s, const double* B, double* X, int
         if (rc != COLA_OK) return rc;
         {
             ProfScope ps2(op->prof, "pcg_update", st);
-            HIP_TRY(pcg_update(x, r, p, q, n, nrhs, w.cg, w.partials, ps, w.counters, w.cnt, vb, st));
+            HIP_TRY(pcg_update(x, r, p, q, n, nrhs, w.cg, w.partials, ps, w.counters, w.cnt, vb, st, w.rh));
         }
         rc = precondition();
         if (rc != COLA_OK) return rc;
     }
     HIP_TRY(pcg_finish(w.cg, nrhs, st));
+    rc = true_residual(op, s, B, x, nrhs, st);            // relres_true of the returned x
+    if (rc != COLA_OK) return rc;
     if (X) HIP_TRY(copy_f64(x, X, (int64_t)nrhs * n, st));
     if (info) HIP_TRY(write_info(info, nullptr, w.cg, nrhs, st));
     return COLA_OK;
@@ -849,10 +879,17 @@ int32_t solve_system(cola_op_s* op, const SysInfo& s, const double* B, double* X
         double* p = (double*)w.vp;
         double* q = (double*)w.vq;
         double* x = (double*)w.vx;     // workspace iterate: captured graphs never hold caller pointers
-        HIP_TRY(cg_prepare<double>(B, r, x, p, n, nrhs, nullptr, w.cg, o->tol, o->max_iters, 0.0, w.partials, ps,
-                                   w.counters, w.cnt, st));
+        const bool warm = o->x0_given && X;
+        if (warm) {
+            int32_t rc = warm_start64(op, s, B, X, x, nrhs, st);
+            if (rc != COLA_OK) return rc;
+        }
+        HIP_TRY(cg_prepare<double>(warm ? w.r64 : B, r, x, p, n, nrhs, nullptr, w.cg, o->tol, o->max_iters, 0.0,
+                                   w.partials, ps, w.counters, w.cnt, st, warm, warm));
         int32_t rc = run_cg<double>(op, s, COLA_PREC_FP64, nrhs, x, r, p, q, o->max_iters, o->check_every, nullptr,
                                     st);
+        if (rc != COLA_OK) return rc;
+        rc = true_residual(op, s, B, x, nrhs, st);       // relres_true of the returned x
         if (rc != COLA_OK) return rc;
         if (X) HIP_TRY(copy_f64(x, X, (int64_t)nrhs * n, st));
         if (info) HIP_TRY(write_info(info, nullptr, w.cg, nrhs, st));
@@ -867,13 +904,22 @@ int32_t solve_system(cola_op_s* op, const SysInfo& s, const double* B, double* X
         // residual whenever it has dropped by inner_tol (reliable updates)
         // the FP64 solution and right-hand side live in the workspace so the
         // captured chunk graphs never hold caller pointers
-        HIP_TRY(fill_f64(w.x64, 0.0, (int64_t)nrhs * n, st));
+        const bool warm = o->x0_given && X;
+        if (warm) HIP_TRY(copy_f64(X, w.x64, (int64_t)nrhs * n, st));
+        else HIP_TRY(fill_f64(w.x64, 0.0, (int64_t)nrhs * n, st));
         HIP_TRY(copy_f64(B, w.b64, (int64_t)nrhs * n, st));
         HIP_TRY(fill_i32(&w.cnt->num_active, 0, 1, st));
+        if (warm) {
+            // the low-precision CG solves for the correction to x0: its right-hand side is
+            // r0 = b - A x0 (FP64), its tolerance stays relative to ||b||
+            HIP_TRY(rhs_norm2(w.b64, n, nrhs, w.cg, w.partials, ps, w.counters, st));
+            int32_t rc = true_residual(op, s, w.b64, w.x64, nrhs, st);
+            if (rc != COLA_OK) return rc;
+        }
         // plain BF16 operands: restart the direction at each update (signalled by a negative delta)
         const double delta = (op->prec == COLA_PREC_BF16) ? -o->inner_tol : o->inner_tol;
-        HIP_TRY(cg_prepare<float>(w.b64, rl, xl, pl, n, nrhs, nullptr, w.cg, o->tol, o->max_iters, delta,
-                                  w.partials, ps, w.counters, w.cnt, st));
+        HIP_TRY(cg_prepare<float>(warm ? w.r64 : w.b64, rl, xl, pl, n, nrhs, nullptr, w.cg, o->tol, o->max_iters,
+                                  delta, w.partials, ps, w.counters, w.cnt, st, false, warm));
         ReliableTail tail{w.x64, w.b64, xl, rl, pl};
         int32_t rc = run_cg<float>(op, s, op->prec, nrhs, xl, rl, pl, ql, o->max_iters, o->check_every, &tail, st);
         if (rc != COLA_OK) return rc;
@@ -885,7 +931,8 @@ int32_t solve_system(cola_op_s* op, const SysInfo& s, const double* B, double* X
     }
     // restarted iterative refinement: FP64 residual, working-precision inner CG
     HIP_TRY(fill_i32(&w.cnt->num_outer_active, 0, 1, st));
-    HIP_TRY(outer_init(B, X, n, nrhs, w.outer, o->tol, o->max_sweeps, w.partials, ps, w.counters, w.cnt, st));
+    HIP_TRY(outer_init(B, X, n, nrhs, w.outer, o->tol, o->max_sweeps, w.partials, ps, w.counters, w.cnt, st,
+                       o->x0_given != 0));
     for (int sweep = 0; sweep <= o->max_sweeps; ++sweep) {
         PassArgs a = base_args(op);
         a.outer = w.outer;
@@ -1074,6 +1121,12 @@ int32_t solve_small(cola_op_s* op, const double* B, double* X, int nrhs, const c
     a.tol = o->tol;
     a.max_iters = o->max_iters;
     a.info = info;
+    a.x0_given = o->x0_given ? 1 : 0;
+    if (o->hist && o->hist_stride > 0 && o->hist_len > 0) {
+        a.rh.data = o->hist;
+        a.rh.stride = o->hist_stride;
+        a.rh.len = o->hist_len;
+    }
     ProfScope ps(op->prof, "small_cg64", st);
     HIP_TRY(launch_small_cg64(a, st));
     return COLA_OK;
@@ -1114,6 +1167,7 @@ int32_t check_opts(const cola_op_s* op, const cola_solve_opts* o) {
     if (!finite_pos(o->tol) || o->max_iters < 1 || o->check_every < 0) return COLA_ERR_INVALID_ARG;
     if (o->precond < COLA_PRECOND_NONE || o->precond > COLA_PRECOND_KRON_EIG) return COLA_ERR_INVALID_ARG;
     if (o->precond != COLA_PRECOND_NONE && o->prec != COLA_PREC_FP64) return COLA_ERR_UNSUPPORTED;
+    if (o->hist && (o->hist_stride < 1 || o->hist_len < 1)) return COLA_ERR_INVALID_ARG;
     if (o->prec != COLA_PREC_FP64) {
         if (o->prec != op->prec) return COLA_ERR_INVALID_ARG;
         if (!finite_pos(o->inner_tol) || o->inner_tol >= 1.0) return COLA_ERR_INVALID_ARG;
@@ -1534,8 +1588,11 @@ int32_t cola_cg_solve(cola_op_t op, const double* B, double* X, int32_t nrhs, co
     int32_t rc = check_opts(op, opts);
     if (rc != COLA_OK) return rc;
     hipStream_t st = S(stream);
+    const bool want_hist = opts->hist != nullptr;
+    if (want_hist)
+        HIP_TRY(fill_f64(opts->hist, __builtin_nan(""), (int64_t)op->sys.size() * nrhs * opts->hist_len, st));
     if (op->resident_ok && op->use_resident && opts->prec == COLA_PREC_FP32 &&
-        opts->refine == COLA_REFINE_RELIABLE)
+        opts->refine == COLA_REFINE_RELIABLE && !opts->x0_given && !want_hist)
         return solve_resident(op, B, X, nrhs, opts, info, st);
     if (op->small_ok && op->use_small && opts->prec == COLA_PREC_FP64 && opts->precond == COLA_PRECOND_NONE)
         return solve_small(op, B, X, nrhs, opts, info, st);
@@ -1544,7 +1601,14 @@ int32_t cola_cg_solve(cola_op_t op, const double* B, double* X, int32_t nrhs, co
     for (size_t i = 0; i < op->sys.size(); ++i) {
         const SysInfo& s = op->sys[i];
         const size_t off = (size_t)nrhs * s.vec_off;
+        op->ws.rh = ResHist{};
+        if (want_hist) {
+            op->ws.rh.data = opts->hist + i * (size_t)nrhs * opts->hist_len;
+            op->ws.rh.stride = opts->hist_stride;
+            op->ws.rh.len = opts->hist_len;
+        }
         rc = solve_system(op, s, B + off, X + off, nrhs, opts, info ? info + i * nrhs : nullptr, st);
+        op->ws.rh = ResHist{};
         if (rc != COLA_OK) return rc;
     }
     return COLA_OK;
@@ -1604,6 +1668,26 @@ int32_t cola_cg_solve_backward(cola_op_t op, const double* X, const double* G, i
         const size_t off = (size_t)nrhs * s.vec_off;
         rc = grad_system(op, s, X + off, Lambda + off, nrhs, dfactors ? dfactors + s.grad_off : nullptr,
                          ddiag ? ddiag[i] : nullptr, dsigma2 ? dsigma2 + i : nullptr, st);
+        if (rc != COLA_OK) return rc;
+    }
+    return COLA_OK;
+}
+
+int32_t cola_logdet_grad(cola_op_t op, const double* Z, int32_t nprobes, const cola_solve_opts* opts,
+                         double* Lambda, void* const* dfactors, void* const* ddiag, double* dsigma2,
+                         cola_solve_info* info, void* stream) {
+    if (!op || !Z || !Lambda || nprobes < 1) return COLA_ERR_INVALID_ARG;
+    int32_t rc = cola_cg_solve(op, Z, Lambda, nprobes, opts, info, stream);      // Lambda = A^{-1} Z
+    if (rc != COLA_OK) return rc;
+    hipStream_t st = S(stream);
+    rc = ensure_ws(op, nprobes, st);
+    if (rc != COLA_OK) return rc;
+    const double scale = -1.0 / nprobes;        // the solve VJP's sign and the mean over probes
+    for (size_t i = 0; i < op->sys.size(); ++i) {
+        const SysInfo& s = op->sys[i];
+        const size_t off = (size_t)nprobes * s.vec_off;
+        rc = grad_system(op, s, Z + off, Lambda + off, nprobes, dfactors ? dfactors + s.grad_off : nullptr,
+                         ddiag ? ddiag[i] : nullptr, dsigma2 ? dsigma2 + i : nullptr, st, scale);
         if (rc != COLA_OK) return rc;
     }
     return COLA_OK;

@@ -54,6 +54,14 @@ struct OuterState {
     int32_t max_sweeps;
 };
 
+// Residual history of a solve: row g (one right-hand side) of `data` receives the
+// recursive relative residual after every `stride` iterations, `len` entries.
+struct ResHist {
+    double* data = nullptr;
+    int32_t stride = 0;
+    int32_t len = 0;
+};
+
 // Counters shared by all RHS of a solve (device memory).
 struct SolveCounters {
     int32_t num_active;       // RHS still iterating in the current inner solve
@@ -159,6 +167,15 @@ __device__ inline bool last_block_reduce8(double partial, double* partials, uint
     if (threadIdx.x == 0) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     *total = t;
     return true;
+}
+
+// Residual history: every `stride` iterations the recursive relative residual sqrt(rho / ||b||^2)
+// (the absolute one for b = 0) at entry iters / stride - 1 of this right-hand side's row.
+__device__ inline void record_residual(const ResHist& h, int64_t g, const CgState& st, double rho) {
+    if (!h.data || h.stride <= 0 || st.iters % h.stride != 0) return;
+    const int k = st.iters / h.stride - 1;
+    if (k < 0 || k >= h.len) return;
+    h.data[g * h.len + k] = st.bnorm2 > 0.0 ? sqrt(rho / st.bnorm2) : sqrt(rho);
 }
 
 // After a reliable update has put ||b - A x||^2 into st.rho_true (x already

@@ -4,9 +4,10 @@
 
 namespace cola {
 
-// Factor, diagonal and sigma2 gradients of one system from X and Lambda = A^{-1} G.
+// Factor, diagonal and sigma2 gradients of one system from X and Lambda = A^{-1} G, times `scale`
+// (1 for the solve VJP; -1/N for the Hutchinson estimate of the log det gradient over N probes).
 int32_t grad_system(cola_op_s* op, const SysInfo& s, const double* X, const double* Lam, int nrhs,
-                    void* const* dfactors, void* ddiag, double* dsigma2, hipStream_t st);
+                    void* const* dfactors, void* ddiag, double* dsigma2, hipStream_t st, double scale = 1.0);
 
 // Time every tile candidate of every contraction pass of this op at nrhs.
 int32_t autotune_op(cola_op_s* op, int nrhs, hipStream_t st);

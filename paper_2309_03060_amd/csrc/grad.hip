@@ -113,31 +113,31 @@ __global__ __launch_bounds__(kThreads) void k_grad_gemm(const double* L, const d
             }
 }
 
-// dK = -sum_c partial[c]
-__global__ void k_grad_reduce(const double* partial, int64_t nchunks, int64_t nn, double* dK) {
+// dK = scale * (-sum_c partial[c])
+__global__ void k_grad_reduce(const double* partial, int64_t nchunks, int64_t nn, double* dK, double scale) {
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nn; e += (int64_t)gridDim.x * blockDim.x) {
         double s = 0.0;
         for (int64_t c = 0; c < nchunks; ++c) s += partial[c * nn + e];
-        dK[e] = -s;
+        dK[e] = -s * scale;
     }
 }
 
-// dd[e] = -sum_r lambda_r[e] x_r[e];  dsigma2 = -sum_e sum_r lambda_r[e] x_r[e]
+// dd[e] = scale * (-sum_r lambda_r[e] x_r[e]);  dsigma2 = scale * (-sum_e sum_r lambda_r[e] x_r[e])
 __global__ __launch_bounds__(kThreads) void k_grad_diag(const double* X, const double* Lam, int64_t n, int nrhs,
                                                         double* dd, double* dsigma2, double* partials,
-                                                        uint32_t* counter) {
+                                                        uint32_t* counter, double scale) {
     __shared__ double red[4];
     double tot_local = 0.0;
     for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n; e += (int64_t)gridDim.x * kThreads) {
         double s = 0.0;
         for (int r = 0; r < nrhs; ++r) s += Lam[(int64_t)r * n + e] * X[(int64_t)r * n + e];
-        if (dd) dd[e] = -s;
+        if (dd) dd[e] = -s * scale;
         tot_local += s;
     }
     const double b = block_sum(tot_local, red);
     double tot;
     if (last_block_reduce(b, partials, counter, gridDim.x, blockIdx.x, &tot, red) && threadIdx.x == 0 && dsigma2)
-        *dsigma2 = -tot;
+        *dsigma2 = -tot * scale;
 }
 
 // ---------------------------------------------------------------------------
@@ -185,7 +185,7 @@ int32_t apply_modes_f64(cola_op_s* op, const SysInfo& s, int term, int skip, con
 }
 
 int32_t grad_system(cola_op_s* op, const SysInfo& s, const double* X, const double* Lam, int nrhs,
-                    void* const* dfactors, void* ddiag, double* dsigma2, hipStream_t st) {
+                    void* const* dfactors, void* ddiag, double* dsigma2, hipStream_t st, double scale) {
     if (op->ws.nrhs < nrhs) return COLA_ERR_INVALID_ARG;    // staging buffers must hold nrhs vectors
     if (dfactors) {
         double* Z = (double*)op->ws.inter[0];
@@ -243,14 +243,14 @@ int32_t grad_system(cola_op_s* op, const SysInfo& s, const double* X, const doub
                 if (hipGetLastError() != hipSuccess) return COLA_ERR_HIP;
                 const int64_t nn = nk * nk;
                 hipLaunchKernelGGL(k_grad_reduce, dim3((unsigned)std::min<int64_t>((nn + 255) / 256, 4096)), dim3(256),
-                                   0, st, partial, chunks, nn, dK);
+                                   0, st, partial, chunks, nn, dK, scale);
                 if (hipGetLastError() != hipSuccess) return COLA_ERR_HIP;
             }
     }
     if (ddiag || dsigma2) {
         const unsigned blocks = (unsigned)std::min<int64_t>(512, std::max<int64_t>(1, (s.n + 2047) / 2048));
         hipLaunchKernelGGL(k_grad_diag, dim3(blocks), dim3(kThreads), 0, st, X, Lam, s.n, nrhs, (double*)ddiag,
-                           dsigma2, op->ws.partials, op->ws.counters);
+                           dsigma2, op->ws.partials, op->ws.counters, scale);
         if (hipGetLastError() != hipSuccess) return COLA_ERR_HIP;
     }
     return COLA_OK;

@@ -43,6 +43,7 @@ struct Workspace {
     int32_t* host_flag = nullptr;     // pinned
     double* hist = nullptr;           // while set: (alpha, beta) of every FP64 CG iteration, hist_len per RHS
     int hist_len = 0;
+    ResHist rh;                       // while set: residual history of the current solve (its system's rows)
 };
 
 // Per-kernel-class timing with HIP events recorded around launches.  Direct
@@ -80,10 +81,11 @@ struct GraphSet {
 };
 struct GraphKey {
     const void* sys; int prec; int nrhs; const void* x; const void* r; const void* p; const void* q;
-    int chunk; int profiled; int tiles_version; const void* hist;
+    int chunk; int profiled; int tiles_version; const void* hist; const void* rhist; int rstride; int rlen;
     bool operator<(const GraphKey& o) const {
-        return std::tie(sys, prec, nrhs, x, r, p, q, chunk, profiled, tiles_version, hist) <
-               std::tie(o.sys, o.prec, o.nrhs, o.x, o.r, o.p, o.q, o.chunk, o.profiled, o.tiles_version, o.hist);
+        return std::tie(sys, prec, nrhs, x, r, p, q, chunk, profiled, tiles_version, hist, rhist, rstride, rlen) <
+               std::tie(o.sys, o.prec, o.nrhs, o.x, o.r, o.p, o.q, o.chunk, o.profiled, o.tiles_version, o.hist,
+                        o.rhist, o.rstride, o.rlen);
     }
 };
 

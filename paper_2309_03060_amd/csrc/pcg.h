@@ -25,10 +25,11 @@ hipError_t trace_shift(const DiagArgs& a, double* out, hipStream_t s);
 
 // x += alpha p, r -= alpha q for the active right-hand sides; the last block of
 // each sums r.r, counts the iteration and decides convergence (r.r <= tol2),
-// the iteration limit or non-finite values, as plain CG does.
+// the iteration limit or non-finite values, as plain CG does; rh records the
+// residual history (or is empty).
 hipError_t pcg_update(double* x, double* r, const double* p, const double* q, int64_t n, int nrhs, CgState* cg,
                       double* partials, int part_stride, uint32_t* counters, SolveCounters* cnt, int max_blocks,
-                      hipStream_t s);
+                      hipStream_t s, ResHist rh = ResHist{});
 
 // z = dinv . r when dinv is given (else z already holds M^{-1} r); rho' = r.z,
 // beta = rho' / rho, rho = rho' for the active right-hand sides; rho' <= 0 or

@@ -66,7 +66,7 @@ __global__ __launch_bounds__(kThreads) void k_trace_shift(DiagArgs a, double* ou
 
 __global__ __launch_bounds__(kThreads) void k_pcg_update(double* x, double* r, const double* p, const double* q,
                                                          int64_t n, CgState* cg, double* partials, int part_stride,
-                                                         uint32_t* counters, SolveCounters* cnt) {
+                                                         uint32_t* counters, SolveCounters* cnt, ResHist rh) {
     __shared__ double red[4];
     const int64_t g = blockIdx.y;
     if (!cg[g].active) return;
@@ -89,6 +89,7 @@ __global__ __launch_bounds__(kThreads) void k_pcg_update(double* x, double* r, c
         CgState& st = cg[g];
         st.iters += 1;
         st.rho_true = tot;                          // r.r (rho holds r.z)
+        record_residual(rh, g, st, tot);
         bool stop = true;
         if (!finite_d(tot)) st.status = COLA_ERR_NONFINITE;
         else if (tot <= st.tol2) st.status = COLA_OK;
@@ -175,10 +176,10 @@ hipError_t trace_shift(const DiagArgs& a, double* out, hipStream_t s) {
 
 hipError_t pcg_update(double* x, double* r, const double* p, const double* q, int64_t n, int nrhs, CgState* cg,
                       double* partials, int part_stride, uint32_t* counters, SolveCounters* cnt, int max_blocks,
-                      hipStream_t s) {
+                      hipStream_t s, ResHist rh) {
     dim3 grid(blocks_for(n, max_blocks < part_stride ? max_blocks : part_stride), nrhs);
     hipLaunchKernelGGL(k_pcg_update, grid, dim3(kThreads), 0, s, x, r, p, q, n, cg, partials, part_stride,
-                       counters, cnt);
+                       counters, cnt, rh);
     return hipGetLastError();
 }
 

@@ -17,10 +17,12 @@ struct SmallArgs {
     double* X;               // packed solutions
     double tol;
     int32_t max_iters;
+    int32_t x0_given;        // X holds the initial iterate (warm start); else x0 = 0
     cola_solve_info* info;   // one per item (system-major), or null
+    ResHist rh;              // residual history, row = item (or empty)
 };
 
-// Whole FP64 CG solves (textbook recurrence, x0 = 0) of K1 (x) K2 + diag(d) + sigma2 I
+// Whole FP64 CG solves (textbook recurrence, from x0 = 0 or the caller's X) of K1 (x) K2 + diag(d) + sigma2 I
 // with both modes <= kSmallMax, one 1024-thread workgroup per item: the factors,
 // the direction and the mode-2 product stay in LDS, x, r and the own part of p
 // in registers, for every iteration.

@@ -68,32 +68,16 @@ __global__ __launch_bounds__(kST) void k_small_cg64(SmallArgs a) {
         K2T[r * PB + c] = (r < n2 && c < n2) ? K2[c * n2 + r] : 0.0;
     }
     for (int e = tid; e < SM * PA; e += kST) Ps[e] = 0.0;
+    __syncthreads();                                         // factors staged before the first product
 
     // this thread's elements: the MFMA output layout of tile (ti, tj), element v at
     // row 16 ti + 4 v + lane / 16, column 16 tj + lane % 16
     const int j = 16 * tj + lr;
-    double x[4], r[4], p[4], dd[4];
-    double bb = 0.0;
+    // q = A v for this thread's four elements of v: both mode products on the matrix cores
+    // through LDS (every thread calls it; its barriers also separate the block sums around it)
+    auto apply = [&](const double (&v4)[4], const double (&dd)[4], double (&q)[4]) {
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-        const int i = 16 * ti + 4 * v + lk;
-        const bool own = i < n1 && j < n2;
-        const int64_t e = (int64_t)i * n2 + j;
-        r[v] = own ? a.B[base + e] : 0.0;
-        x[v] = 0.0;
-        p[v] = r[v];
-        dd[v] = own ? sy.sigma2 + (sy.diag_off >= 0 ? a.diag64[sy.diag_off + e] : 0.0) : 0.0;
-        bb += r[v] * r[v];
-    }
-    bb = block_sum_small(bb, red_rr);
-    const double tol2 = a.tol * a.tol * bb;
-    double rho = bb;
-    int iters = 0, status = COLA_NOT_CONVERGED;
-    if (!__builtin_isfinite(bb)) status = COLA_ERR_NONFINITE;
-    else if (bb <= tol2) status = COLA_OK;                  // includes b = 0: x = 0 after zero iterations
-    while (status == COLA_NOT_CONVERGED && iters < a.max_iters) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) Ps[(16 * ti + 4 * v + lk) * PA + j] = p[v];
+        for (int v = 0; v < 4; ++v) Ps[(16 * ti + 4 * v + lk) * PA + j] = v4[v];
         __syncthreads();                                     // P complete
         doublex4 acc = {0.0, 0.0, 0.0, 0.0};
         for (int kb = 0; kb < k2max; kb += 16) {             // T = P K2^T
@@ -120,12 +104,47 @@ __global__ __launch_bounds__(kST) void k_small_cg64(SmallArgs a) {
 #pragma unroll
             for (int s = 0; s < 4; ++s) acc = mma64(av[s], bv[s], acc);
         }
-        double q[4], pq = 0.0;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) q[v] = fma(dd[v], v4[v], acc[v]);
+    };
+    double x[4], r[4], p[4], dd[4], bvals[4], q[4];
+    double bb = 0.0;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int i = 16 * ti + 4 * v + lk;
+        const bool own = i < n1 && j < n2;
+        const int64_t e = (int64_t)i * n2 + j;
+        bvals[v] = own ? a.B[base + e] : 0.0;
+        x[v] = (own && a.x0_given) ? a.X[base + e] : 0.0;
+        dd[v] = own ? sy.sigma2 + (sy.diag_off >= 0 ? a.diag64[sy.diag_off + e] : 0.0) : 0.0;
+        bb += bvals[v] * bvals[v];
+    }
+    bb = block_sum_small(bb, red_rr);
+    double rho = bb;
+    if (a.x0_given) {                                        // warm start: r0 = b - A x0
+        apply(x, dd, q);
+        double rr = 0.0;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            q[v] = fma(dd[v], p[v], acc[v]);
-            pq += p[v] * q[v];
+            r[v] = bvals[v] - q[v];
+            rr += r[v] * r[v];
         }
+        rho = block_sum_small(rr, red_pq);
+    } else {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) r[v] = bvals[v];
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) p[v] = r[v];
+    const double tol2 = a.tol * a.tol * bb;
+    int iters = 0, status = COLA_NOT_CONVERGED;
+    if (!__builtin_isfinite(bb) || !__builtin_isfinite(rho)) status = COLA_ERR_NONFINITE;
+    else if (rho <= tol2) status = COLA_OK;                  // includes b = 0 (x = 0) after zero iterations
+    while (status == COLA_NOT_CONVERGED && iters < a.max_iters) {
+        apply(p, dd, q);
+        double pq = 0.0;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) pq += p[v] * q[v];
         pq = block_sum_small(pq, red_pq);
         if (!(pq > 0.0) || !__builtin_isfinite(pq)) {
             status = __builtin_isfinite(pq) ? COLA_ERR_NOT_SPD : COLA_ERR_NONFINITE;
@@ -143,11 +162,22 @@ __global__ __launch_bounds__(kST) void k_small_cg64(SmallArgs a) {
         ++iters;
         const double beta = rr / rho;
         rho = rr;
+        if (a.rh.data && tid == 0 && iters % a.rh.stride == 0 && iters / a.rh.stride <= a.rh.len)
+            a.rh.data[(int64_t)item * a.rh.len + iters / a.rh.stride - 1] = bb > 0.0 ? sqrt(rr / bb) : sqrt(rr);
         if (!__builtin_isfinite(rr)) status = COLA_ERR_NONFINITE;
         else if (rr <= tol2) status = COLA_OK;
 #pragma unroll
         for (int v = 0; v < 4; ++v) p[v] = fma(beta, p[v], r[v]);
     }
+    // the FP64 true residual of the returned x
+    apply(x, dd, q);
+    double rt = 0.0;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const double e = bvals[v] - q[v];
+        rt += e * e;
+    }
+    rt = block_sum_small(rt, red_pq);
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
         const int i = 16 * ti + 4 * v + lk;
@@ -159,7 +189,8 @@ __global__ __launch_bounds__(kST) void k_small_cg64(SmallArgs a) {
         o.iters = iters;
         o.sweeps = 0;
         o.reserved = 0;
-        o.relres = bb > 0.0 ? sqrt(rho / bb) : sqrt(rho);
+        o.relres_recursive = bb > 0.0 ? sqrt(rho / bb) : sqrt(rho);
+        o.relres_true = bb > 0.0 ? sqrt(rt / bb) : sqrt(rt);
         a.info[item] = o;
     }
 }

@@ -41,7 +41,7 @@ __global__ void k_copy_f64(const double* in, double* out, int64_t n) {
 __global__ __launch_bounds__(kThreads) void k_outer_init(const double* B, double* X, int64_t n,
                                                          OuterState* outer, double tol, int max_sweeps,
                                                          double* partials, int part_stride,
-                                                         uint32_t* counters, SolveCounters* cnt) {
+                                                         uint32_t* counters, SolveCounters* cnt, int keep_x) {
     __shared__ double red[4];
     const int64_t g = blockIdx.y;
     const double* b = B + g * n;
@@ -50,7 +50,7 @@ __global__ __launch_bounds__(kThreads) void k_outer_init(const double* B, double
     for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
         const double v = b[i];
         s += v * v;
-        x[i] = 0.0;
+        if (!keep_x) x[i] = 0.0;
     }
     s = block_sum(s, red);
     double tot;
@@ -81,11 +81,14 @@ __global__ __launch_bounds__(kThreads) void k_outer_init(const double* B, double
 // Start a CG solve on rhs = src * scale (scale = 1 / ||r|| of the refinement
 // residual, or 1): r = rhs, x = 0, p = 0 (so the first direction r + 0 p = r),
 // rho = ||r||^2, stop threshold tol^2 ||rhs||^2.
+// keep_x: leave x as it is (a warm start, x = x0 with src = b - A x0);
+// keep_bnorm: cg.bnorm2 already holds ||b||^2 (tolerances stay relative to b, not to src).
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_cg_prepare(const double* src, T* r, T* x, T* p, int64_t n,
                                                          const OuterState* outer, CgState* cg, double tol,
                                                          int max_iters, double delta, double* partials,
-                                                         int part_stride, uint32_t* counters, SolveCounters* cnt) {
+                                                         int part_stride, uint32_t* counters, SolveCounters* cnt,
+                                                         int keep_x, int keep_bnorm) {
     __shared__ double red[4];
     const int64_t g = blockIdx.y;
     if (outer && !outer[g].active) {
@@ -105,7 +108,7 @@ __global__ __launch_bounds__(kThreads) void k_cg_prepare(const double* src, T* r
     for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
         const T v = (T)(sg[i] * scale);
         rg[i] = v;
-        xg[i] = (T)0;
+        if (!keep_x) xg[i] = (T)0;
         pg[i] = (T)0;
         s += (double)v * (double)v;
     }
@@ -115,8 +118,8 @@ __global__ __launch_bounds__(kThreads) void k_cg_prepare(const double* src, T* r
         threadIdx.x == 0) {
         CgState& st = cg[g];
         st.rho = tot;
-        st.bnorm2 = tot;
-        st.tol2 = tol * tol * tot;
+        if (!keep_bnorm) st.bnorm2 = tot;
+        st.tol2 = tol * tol * st.bnorm2;
         st.alpha = 0.0;
         st.beta = 0.0;
         st.iters = 0;
@@ -144,13 +147,29 @@ __global__ __launch_bounds__(kThreads) void k_cg_prepare(const double* src, T* r
     }
 }
 
+// cg.bnorm2 = ||b||^2 per right-hand side (the reference of a warm-started solve's tolerance).
+__global__ __launch_bounds__(kThreads) void k_rhs_norm2(const double* B, int64_t n, CgState* cg, double* partials,
+                                                        int part_stride, uint32_t* counters) {
+    __shared__ double red[4];
+    const int64_t g = blockIdx.y;
+    const double* bg = B + g * n;
+    double s = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads)
+        s += bg[i] * bg[i];
+    s = block_sum(s, red);
+    double tot;
+    if (last_block_reduce(s, partials + g * part_stride, counters + g, gridDim.x, blockIdx.x, &tot, red) &&
+        threadIdx.x == 0)
+        cg[g].bnorm2 = tot;
+}
+
 // ---------------------------------------------------------------------------
 // x += alpha p;  r -= alpha q;  rho' = r.r (FP64);  last block: convergence test and beta.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_cg_update(T* x, T* r, const T* p, const T* q, int64_t n,
                                                         CgState* cg, double* partials, int part_stride,
                                                         uint32_t* counters, SolveCounters* cnt, double* hist,
-                                                        int hist_len) {
+                                                        int hist_len, ResHist rh) {
     __shared__ double red[4];
     const int64_t g = blockIdx.y;
     if (!cg[g].active) return;
@@ -207,6 +226,7 @@ __global__ __launch_bounds__(kThreads) void k_cg_update(T* x, T* r, const T* p, 
             h[0] = st.alpha;
             h[1] = tot / st.rho;
         }
+        record_residual(rh, g, st, tot);
         bool stop = true;
         if (!finite_d(tot)) {
             st.status = COLA_ERR_NONFINITE;
@@ -305,28 +325,28 @@ __global__ __launch_bounds__(kThreads) void k_reliable_apply(const double* r64, 
     }
 }
 
-// Public per-RHS outcome.
+// Public per-RHS outcome: the recursive residual of the (inner) CG and the FP64
+// true residual of the returned x.
 __global__ void k_write_info(cola_solve_info* info, const OuterState* outer, const CgState* cg, int nrhs) {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= nrhs) return;
     cola_solve_info o;
-    if (outer) {
+    if (outer) {                                 // restarted refinement: its test is on the true residual
         o.status = outer[g].status;
         o.iters = outer[g].iters;
         o.sweeps = outer[g].sweeps;
-        o.relres = outer[g].relres;
-    } else if (cg[g].delta > 0.0) {             // reliable updates: report the true residual
-        o.status = cg[g].status;
-        o.iters = cg[g].iters;
-        o.sweeps = cg[g].updates;
-        o.relres = cg[g].bnorm2 > 0.0 ? sqrt(cg[g].rho_true / cg[g].bnorm2) : sqrt(cg[g].rho_true);
-        if (o.status == COLA_NOT_CONVERGED && cg[g].bnorm2 > 0.0 && cg[g].rho_true <= cg[g].tol2)
-            o.status = COLA_OK;
+        o.relres_recursive = outer[g].relres;
+        o.relres_true = outer[g].relres;
     } else {
-        o.status = cg[g].status;
-        o.iters = cg[g].iters;
-        o.sweeps = 0;
-        o.relres = cg[g].bnorm2 > 0.0 ? sqrt(cg[g].rho / cg[g].bnorm2) : sqrt(cg[g].rho);
+        const CgState& st = cg[g];
+        const double b2 = st.bnorm2;
+        o.status = st.status;
+        o.iters = st.iters;
+        o.sweeps = st.delta > 0.0 ? st.updates : 0;
+        o.relres_recursive = b2 > 0.0 ? sqrt(st.rho / b2) : sqrt(st.rho);
+        o.relres_true = b2 > 0.0 ? sqrt(st.rho_true / b2) : sqrt(st.rho_true);
+        // reliable updates stop on the true residual
+        if (st.delta > 0.0 && o.status == COLA_NOT_CONVERGED && b2 > 0.0 && st.rho_true <= st.tol2) o.status = COLA_OK;
     }
     o.reserved = 0;
     info[g] = o;
@@ -393,28 +413,35 @@ hipError_t fill_f32(float* p, float v, int64_t n, hipStream_t s) {
 
 hipError_t outer_init(const double* B, double* X, int64_t n, int nrhs, OuterState* outer, double tol,
                       int max_sweeps, double* partials, int part_stride, uint32_t* counters,
-                      SolveCounters* cnt, hipStream_t s) {
+                      SolveCounters* cnt, hipStream_t s, bool keep_x) {
     dim3 grid(vec_blocks_per_rhs(n), nrhs);
     hipLaunchKernelGGL(k_outer_init, grid, dim3(kThreads), 0, s, B, X, n, outer, tol, max_sweeps,
-                       partials, part_stride, counters, cnt);
+                       partials, part_stride, counters, cnt, keep_x ? 1 : 0);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t cg_prepare(const double* src, T* r, T* x, T* p, int64_t n, int nrhs, const OuterState* outer,
                       CgState* cg, double tol, int max_iters, double delta, double* partials, int part_stride,
-                      uint32_t* counters, SolveCounters* cnt, hipStream_t s) {
+                      uint32_t* counters, SolveCounters* cnt, hipStream_t s, bool keep_x, bool keep_bnorm) {
     dim3 grid(vec_blocks_per_rhs(n), nrhs);
     hipLaunchKernelGGL(k_cg_prepare<T>, grid, dim3(kThreads), 0, s, src, r, x, p, n, outer, cg, tol,
-                       max_iters, delta, partials, part_stride, counters, cnt);
+                       max_iters, delta, partials, part_stride, counters, cnt, keep_x ? 1 : 0, keep_bnorm ? 1 : 0);
     return hipGetLastError();
 }
 template hipError_t cg_prepare<float>(const double*, float*, float*, float*, int64_t, int, const OuterState*,
                                       CgState*, double, int, double, double*, int, uint32_t*, SolveCounters*,
-                                      hipStream_t);
+                                      hipStream_t, bool, bool);
 template hipError_t cg_prepare<double>(const double*, double*, double*, double*, int64_t, int, const OuterState*,
                                        CgState*, double, int, double, double*, int, uint32_t*, SolveCounters*,
-                                       hipStream_t);
+                                       hipStream_t, bool, bool);
+
+hipError_t rhs_norm2(const double* B, int64_t n, int nrhs, CgState* cg, double* partials, int part_stride,
+                     uint32_t* counters, hipStream_t s) {
+    dim3 grid(vec_blocks_per_rhs(n), nrhs);
+    hipLaunchKernelGGL(k_rhs_norm2, grid, dim3(kThreads), 0, s, B, n, cg, partials, part_stride, counters);
+    return hipGetLastError();
+}
 
 template <typename T>
 hipError_t reliable_fold(double* x64, T* xlo, const T* p, int64_t n, int nrhs, const CgState* cg, bool all_rhs,
@@ -440,16 +467,16 @@ template hipError_t reliable_apply<float>(const double*, float*, int64_t, int, C
 template <typename T>
 hipError_t cg_update(T* x, T* r, const T* p, const T* q, int64_t n, int nrhs, CgState* cg, double* partials,
                      int part_stride, uint32_t* counters, SolveCounters* cnt, hipStream_t s, double* hist,
-                     int hist_len) {
+                     int hist_len, ResHist rh) {
     dim3 grid(vec_blocks_per_rhs(n), nrhs);
     hipLaunchKernelGGL(k_cg_update<T>, grid, dim3(kThreads), 0, s, x, r, p, q, n, cg, partials, part_stride,
-                       counters, cnt, hist, hist_len);
+                       counters, cnt, hist, hist_len, rh);
     return hipGetLastError();
 }
 template hipError_t cg_update<float>(float*, float*, const float*, const float*, int64_t, int, CgState*, double*,
-                                     int, uint32_t*, SolveCounters*, hipStream_t, double*, int);
+                                     int, uint32_t*, SolveCounters*, hipStream_t, double*, int, ResHist);
 template hipError_t cg_update<double>(double*, double*, const double*, const double*, int64_t, int, CgState*,
-                                      double*, int, uint32_t*, SolveCounters*, hipStream_t, double*, int);
+                                      double*, int, uint32_t*, SolveCounters*, hipStream_t, double*, int, ResHist);
 
 template <typename T>
 hipError_t refine_accumulate(double* x64, const T* d, int64_t n, int nrhs, const OuterState* outer,

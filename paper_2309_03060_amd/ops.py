@@ -133,8 +133,15 @@ class KronOperator:
         return Y
 
     def _opts(self, tol, max_iters, prec, inner_tol, max_sweeps, check_every, refine="reliable",
-              precond="none") -> L.SolveOpts:
+              precond="none", x0_given=False, hist=None, hist_stride=0) -> L.SolveOpts:
         o = L.SolveOpts()
+        o.x0_given = 1 if x0_given else 0
+        if hist is not None:
+            if hist.dtype != torch.float64 or not hist.is_contiguous() or hist.dim() != 2:
+                raise ValueError("hist must be a contiguous float64 device tensor (nsys * nrhs, length)")
+            o.hist = hist.data_ptr()
+            o.hist_len = int(hist.shape[1])
+            o.hist_stride = int(hist_stride)
         o.refine = L.REFINE_BY_NAME[refine]
         o.precond = L.PRECOND_BY_NAME[precond]
         o.tol = float(tol)
@@ -148,28 +155,31 @@ class KronOperator:
     def solve(self, B: torch.Tensor, nrhs: int, tol: float = 1e-6, max_iters: int = 10000,
               prec: Optional[str] = None, inner_tol: float = 0.1, max_sweeps: int = 20,
               check_every: int = 32, info: Optional[torch.Tensor] = None, refine: str = "reliable",
-              precond: str = "none"):
+              precond: str = "none", x0: Optional[torch.Tensor] = None, hist: Optional[torch.Tensor] = None,
+              hist_stride: int = 1):
         """X = A^{-1} B (cola_cg_solve); returns (X, info tensor on device).  precond ("none",
-        "jacobi", "kron_eig") selects preconditioned CG, FP64 solves only."""
+        "jacobi", "kron_eig") selects preconditioned CG, FP64 solves only.  x0: warm start (packed like
+        B).  hist: (nsys * nrhs, length) float64 device tensor receiving the recursive relative residual
+        every hist_stride iterations (NaN where none was recorded)."""
         if B.dtype != torch.float64 or not B.is_contiguous():
             raise ValueError("B must be a contiguous float64 device tensor")
-        X = torch.empty_like(B)
+        if x0 is not None:
+            if x0.shape != B.shape or x0.dtype != torch.float64:
+                raise ValueError("x0 must be a float64 device tensor shaped like B")
+            X = x0.detach().clone().contiguous()
+        else:
+            X = torch.empty_like(B)
         if info is None:
-            info = torch.empty(len(self.sizes) * nrhs * 6, dtype=torch.int32, device=B.device)
-        o = self._opts(tol, max_iters, prec, inner_tol, max_sweeps, check_every, refine, precond)
+            info = torch.empty(len(self.sizes) * nrhs * L.INFO_WORDS, dtype=torch.int32, device=B.device)
+        o = self._opts(tol, max_iters, prec, inner_tol, max_sweeps, check_every, refine, precond,
+                       x0_given=x0 is not None, hist=hist, hist_stride=hist_stride)
         L.check("cola_cg_solve", self.lib.cola_cg_solve(self.handle, B.data_ptr(), X.data_ptr(), nrhs,
                                                         ctypes.byref(o), info.data_ptr(), _stream_ptr()))
         return X, info
 
-    def solve_backward(self, X: torch.Tensor, G: torch.Tensor, nrhs: int, tol: float = 1e-6,
-                       max_iters: int = 10000, prec: Optional[str] = None, inner_tol: float = 0.1,
-                       max_sweeps: int = 20, check_every: int = 32, want_factors: bool = True,
-                       want_diag: bool = True, refine: str = "reliable", precond: str = "none"):
-        """Adjoint backward (cola_cg_solve_backward): Lambda, dfactors, ddiag, dsigma2, info."""
-        dev = X.device
-        Lam = torch.empty_like(X)
-        dfac = []
-        ptrs = []
+    def _grad_buffers(self, dev, want_factors=True, want_diag=True):
+        """Per-system gradient outputs and the host pointer arrays the C ABI takes."""
+        dfac, ptrs = [], []
         for s in self.systems:
             rows = []
             for row in s.factors:
@@ -180,8 +190,7 @@ class KronOperator:
                     ptrs.append(t.data_ptr())
                 rows.append(r)
             dfac.append(rows)
-        ddiag = []
-        dptrs = []
+        ddiag, dptrs = [], []
         for s in self.systems:
             if s.diag is not None and want_diag:
                 t = torch.empty(s.n, dtype=torch.float64, device=dev)
@@ -191,14 +200,25 @@ class KronOperator:
                 ddiag.append(None)
                 dptrs.append(None)
         ds2 = torch.empty(len(self.systems), dtype=torch.float64, device=dev)
-        info = torch.empty(len(self.sizes) * nrhs * 6, dtype=torch.int32, device=dev)
-        o = self._opts(tol, max_iters, prec, inner_tol, max_sweeps, check_every, refine, precond)
         fa = (ctypes.c_void_p * max(1, len(ptrs)))(*ptrs) if want_factors else None
         da = (ctypes.c_void_p * len(dptrs))(*dptrs)
+        fap = ctypes.cast(fa, ctypes.POINTER(ctypes.c_void_p)) if fa is not None else None
+        dap = ctypes.cast(da, ctypes.POINTER(ctypes.c_void_p))
+        return dfac, ddiag, ds2, (fa, da, fap, dap)
+
+    def solve_backward(self, X: torch.Tensor, G: torch.Tensor, nrhs: int, tol: float = 1e-6,
+                       max_iters: int = 10000, prec: Optional[str] = None, inner_tol: float = 0.1,
+                       max_sweeps: int = 20, check_every: int = 32, want_factors: bool = True,
+                       want_diag: bool = True, refine: str = "reliable", precond: str = "none"):
+        """Adjoint backward (cola_cg_solve_backward): Lambda, dfactors, ddiag, dsigma2, info."""
+        dev = X.device
+        Lam = torch.empty_like(X)
+        dfac, ddiag, ds2, (fa, da, fap, dap) = self._grad_buffers(dev, want_factors, want_diag)
+        info = torch.empty(len(self.sizes) * nrhs * L.INFO_WORDS, dtype=torch.int32, device=dev)
+        o = self._opts(tol, max_iters, prec, inner_tol, max_sweeps, check_every, refine, precond)
         L.check("cola_cg_solve_backward", self.lib.cola_cg_solve_backward(
-            self.handle, X.data_ptr(), G.data_ptr(), nrhs, ctypes.byref(o), Lam.data_ptr(),
-            ctypes.cast(fa, ctypes.POINTER(ctypes.c_void_p)) if fa is not None else None,
-            ctypes.cast(da, ctypes.POINTER(ctypes.c_void_p)), ds2.data_ptr(), info.data_ptr(), _stream_ptr()))
+            self.handle, X.data_ptr(), G.data_ptr(), nrhs, ctypes.byref(o), Lam.data_ptr(), fap, dap,
+            ds2.data_ptr(), info.data_ptr(), _stream_ptr()))
         return Lam, (dfac if want_factors else None), ddiag, ds2, info
 
     def diagonal(self) -> torch.Tensor:
@@ -243,20 +263,27 @@ class KronOperator:
         ld = torch.empty(nsys, dtype=torch.float64, device=Z.device)
         est = torch.empty(nsys * nprobes, dtype=torch.float64, device=Z.device)
         X = torch.empty_like(Z) if want_solution else None
-        info = torch.empty(len(self.sizes) * nprobes * 6, dtype=torch.int32, device=Z.device)
+        info = torch.empty(len(self.sizes) * nprobes * L.INFO_WORDS, dtype=torch.int32, device=Z.device)
         L.check("cola_slq_logdet", self.lib.cola_slq_logdet(
             self.handle, Z.data_ptr(), nprobes, tol, max_iters, X.data_ptr() if X is not None else None,
             ld.data_ptr(), est.data_ptr(), info.data_ptr(), _stream_ptr()))
         return ld, est, X, info
 
-    def logdet_grad(self, Z: torch.Tensor, nprobes: int, tol: float = 1e-8, max_iters: int = 10000):
-        """Hutchinson estimate of d log det A / d(factors, diagonal, sigma2): the mean over probes of
-        (A^{-1} z)^T (dA/dtheta) z, i.e. the adjoint backward with X = G = Z divided by -nprobes."""
-        _, dfac, ddiag, ds2, info = self.solve_backward(Z, Z, nprobes, tol=tol, max_iters=max_iters, prec="fp64")
-        scale = -1.0 / nprobes
-        dfac = [[[g * scale for g in row] for row in sysf] for sysf in dfac]
-        ddiag = [None if d is None else d * scale for d in ddiag]
-        return dfac, ddiag, ds2 * scale, info
+    def logdet_grad(self, Z: torch.Tensor, nprobes: int, tol: float = 1e-8, max_iters: int = 10000,
+                    x0: Optional[torch.Tensor] = None):
+        """Hutchinson estimate of d log det A / d(factors, diagonal, sigma2) (cola_logdet_grad): the mean
+        over probes of (A^{-1} z)^T (dA/dtheta) z.  x0: a warm start for A^{-1} Z (e.g. logdet's X)."""
+        if Z.dtype != torch.float64 or not Z.is_contiguous():
+            raise ValueError("Z must be a contiguous float64 device tensor")
+        dev = Z.device
+        Lam = x0.detach().clone().contiguous() if x0 is not None else torch.empty_like(Z)
+        dfac, ddiag, ds2, (fa, da, fap, dap) = self._grad_buffers(dev)
+        info = torch.empty(len(self.sizes) * nprobes * L.INFO_WORDS, dtype=torch.int32, device=dev)
+        o = self._opts(tol, max_iters, "fp64", 0.1, 20, 32, x0_given=x0 is not None)
+        L.check("cola_logdet_grad", self.lib.cola_logdet_grad(
+            self.handle, Z.data_ptr(), nprobes, ctypes.byref(o), Lam.data_ptr(), fap, dap, ds2.data_ptr(),
+            info.data_ptr(), _stream_ptr()))
+        return dfac, ddiag, ds2, info
 
     def autotune(self, nrhs: int):
         L.check("cola_autotune", self.lib.cola_autotune(self.handle, nrhs, _stream_ptr()))
@@ -287,12 +314,15 @@ class KronOperator:
 
 
 def decode_info(info: torch.Tensor, count: int):
-    """Device info buffer -> list of dicts (status, iters, sweeps, relres)."""
-    raw = info.detach().cpu().numpy().view(np.uint8)[: count * 24]
+    """Device info buffer -> list of dicts (status, iters, sweeps, relres_recursive, relres_true, and
+    relres = the FP64 true residual of the returned X)."""
+    raw = info.detach().cpu().numpy().view(np.uint8)[: count * 4 * L.INFO_WORDS]
     rec = np.frombuffer(raw.tobytes(), dtype=np.dtype([("status", "<i4"), ("iters", "<i4"), ("sweeps", "<i4"),
-                                                        ("reserved", "<i4"), ("relres", "<f8")]))
+                                                        ("reserved", "<i4"), ("relres_recursive", "<f8"),
+                                                        ("relres_true", "<f8")]))
     return [dict(status=int(r["status"]), iters=int(r["iters"]), sweeps=int(r["sweeps"]),
-                 relres=float(r["relres"])) for r in rec]
+                 relres_recursive=float(r["relres_recursive"]), relres_true=float(r["relres_true"]),
+                 relres=float(r["relres_true"])) for r in rec]
 
 
 class KronSolve(torch.autograd.Function):
