@@ -179,7 +179,10 @@ typedef struct {
     int32_t reserved;
     double* hist;         /* NULL, or DEVICE nsys*nrhs*hist_len doubles, row (system, RHS)
                              in packing order, entry k after iteration (k+1)*hist_stride;
-                             the call first fills every entry with NaN                    */
+                             the call first fills every entry with NaN.  Mixed precision
+                             records the working-precision recurrence (reset to the FP64
+                             residual at each reliable update); restarted refinement
+                             records nothing                                              */
 } cola_solve_opts;
 
 /* Per (system, RHS) outcome, written to DEVICE memory in stream order. */

@@ -1598,11 +1598,13 @@ int32_t cola_cg_solve(cola_op_t op, const double* B, double* X, int32_t nrhs, co
         return solve_small(op, B, X, nrhs, opts, info, st);
     rc = ensure_ws(op, nrhs, st);
     if (rc != COLA_OK) return rc;
+    // restarted refinement's inner solves each start over on a normalised residual: no history
+    const bool record = want_hist && !(opts->prec != COLA_PREC_FP64 && opts->refine == COLA_REFINE_RESTART);
     for (size_t i = 0; i < op->sys.size(); ++i) {
         const SysInfo& s = op->sys[i];
         const size_t off = (size_t)nrhs * s.vec_off;
         op->ws.rh = ResHist{};
-        if (want_hist) {
+        if (record) {
             op->ws.rh.data = opts->hist + i * (size_t)nrhs * opts->hist_len;
             op->ws.rh.stride = opts->hist_stride;
             op->ws.rh.len = opts->hist_len;

@@ -179,3 +179,23 @@ def test_history_on_mixed_precision_and_fused_engine():
         assert rec[r]["status"] == 0 and k <= length
         assert np.all(np.isfinite(h[r, :k])) and np.all(np.isnan(h[r, k:]))
         assert h[r, k - 1] <= 1e-5                         # the recurrence's last value (refreshed by updates)
+
+
+def test_restarted_refinement_records_no_history():
+    """Restarted refinement's inner solves each start over on a normalised residual, so its history
+    stays NaN while the solve itself converges as without a history."""
+    import torch
+    from gpu_util import infos, make_op, pack
+    rng = np.random.default_rng(12)
+    s = wl.random_system(rng, (20, 18), nterms=2, diag=True, sigma2=0.2)
+    B = rng.standard_normal((2, s.n))
+    op = make_op([s], prec="fp32")
+    hist = torch.zeros((2, 50), dtype=torch.float64, device="cuda:0")
+    kw = dict(prec="fp32", tol=1e-9, refine="restart", inner_tol=1e-3, max_sweeps=20, max_iters=4000)
+    _, info = op.solve(pack([B]), 2, hist=hist, hist_stride=1, **kw)
+    _, info0 = op.solve(pack([B]), 2, **kw)
+    op.close()
+    rec, rec0 = infos(info, 2), infos(info0, 2)
+    assert all(r["status"] == 0 for r in rec)
+    assert [r["iters"] for r in rec] == [r["iters"] for r in rec0]
+    assert np.all(np.isnan(hist.cpu().numpy()))
