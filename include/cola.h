@@ -327,9 +327,14 @@ int32_t cola_autotune(cola_op_t op, int32_t nrhs, void* stream);
  * COLA_ERR_INVALID_ARG for an unknown engine. */
 #define COLA_ENGINE_FUSED_CG 1  /* persistent CG, one cooperative launch per chunk of iterations:
                                    one-term K1 (x) K2 (x) K3 (+ diag) with 64-wide modes, FP32
-                                   working precision, solves with check_every > 0               */
+                                   working precision, no residual history.  With check_every
+                                   = 0 every chunk of 128 iterations is enqueued up front
+                                   (capture-safe); a barrier time-out, which a captured launch
+                                   can meet if other work shares the GPU, is then reported
+                                   as COLA_ERR_HIP in every right-hand side's info          */
 #define COLA_ENGINE_GEMM2    2  /* dense-GEMM MVM: BF16, two-mode, modes multiples of 256       */
-#define COLA_ENGINE_GEMM3    3  /* dense-GEMM MVM: FP32, one-term three-mode, 256-wide modes    */
+#define COLA_ENGINE_GEMM3    3  /* dense-GEMM MVM: FP32 or BF16x3, one-term three-mode, 256-wide
+                                   modes                                                     */
 #define COLA_ENGINE_SLAB     4  /* fused mode-2/mode-3 products of three-mode terms, modes <= 64 */
 #define COLA_ENGINE_RESIDENT 5  /* resident batched CG of many small two-mode systems           */
 #define COLA_ENGINE_SMALL64  6  /* FP64 solves of one-term two-mode systems with modes <= 64: the

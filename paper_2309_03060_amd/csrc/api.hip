@@ -511,7 +511,7 @@ int32_t ensure_fused(cola_op_s* op) {
 
 bool fused_eligible(const cola_op_s* op, const SysInfo& s, int prec, int check_every) {
     // the persistent kernel runs its own vector update, which records no residual history
-    return op->use_fused && check_every > 0 && op->fused_max_blocks != 0 && prec == op->prec && !op->ws.rh.data &&
+    return op->use_fused && check_every >= 0 && op->fused_max_blocks != 0 && prec == op->prec && !op->ws.rh.data &&
            fused_cg_supported(prec, s.Fv, s.J, s.dims);
 }
 
@@ -519,10 +519,15 @@ bool fused_eligible(const cola_op_s* op, const SysInfo& s, int prec, int check_e
 // every chunk of check_every iterations is one cooperative launch per batch of
 // right-hand sides (then the reliable-update tail), with the host reading the
 // count of active right-hand sides one chunk behind, as in the graph path.
+// check_every == 0: every chunk (128 iterations between reliable updates) is
+// enqueued up front with no host wait, so the caller may capture the solve;
+// groups that are no longer active leave a launch at once, and a barrier
+// time-out is reported per right-hand side instead of by a host check.
 int32_t run_cg_fused(cola_op_s* op, const SysInfo& s, int nrhs, float* x, float* r, float* p, int max_iters,
                      int check_every, const ReliableTail* tail, hipStream_t st) {
     Workspace& w = op->ws;
-    const int chunk = std::min(check_every, max_iters);
+    const bool host_checks = check_every > 0;
+    const int chunk = host_checks ? std::min(check_every, max_iters) : (tail ? std::min(128, max_iters) : max_iters);
     const int nchunks = (max_iters + chunk - 1) / chunk;
     const int bpr = fused_cg_blocks_per_rhs(nrhs, op->fused_max_blocks);
     const int per_launch = op->fused_max_blocks / bpr;
@@ -565,6 +570,7 @@ int32_t run_cg_fused(cola_op_s* op, const SysInfo& s, int nrhs, float* x, float*
             int32_t rc = enqueue_tail(op, s, nrhs, *tail, false, st);
             if (rc != COLA_OK) return rc;
         }
+        if (!host_checks) continue;
         const int b = c & 1;
         HIP_TRY(hipMemcpyAsync(&w.host_flag[b], &w.cnt->num_active, sizeof(int32_t), hipMemcpyDeviceToHost, st));
         HIP_TRY(hipEventRecord(op->fused_done[b], st));
@@ -573,6 +579,10 @@ int32_t run_cg_fused(cola_op_s* op, const SysInfo& s, int nrhs, float* x, float*
             HIP_TRY(hipEventSynchronize(op->fused_done[(c - 1) & 1]));
             if (*(volatile int32_t*)&w.host_flag[(c - 1) & 1] <= 0) break;
         }
+    }
+    if (!host_checks) {
+        HIP_TRY(fused_cg_report_timeout(a.err, w.cg, nrhs, st));
+        return COLA_OK;
     }
     if (last >= 0) HIP_TRY(hipEventSynchronize(op->fused_done[last & 1]));
     uint32_t timed_out = 0;

@@ -37,4 +37,9 @@ int fused_cg_blocks_per_rhs(int nrhs, int max_blocks);
 // Cooperative launch of nrhs * bpr blocks (nrhs * bpr <= fused_cg_max_blocks()).
 hipError_t launch_fused_cg(const FusedCgArgs& a, hipStream_t s);
 
+// After the launches of a solve enqueued without host checks: if a group barrier
+// timed out (*err set), every right-hand side of the solve is reported as
+// COLA_ERR_HIP and stops (the launch's results are void).
+hipError_t fused_cg_report_timeout(const uint32_t* err, CgState* cg, int nrhs, hipStream_t s);
+
 }  // namespace cola

@@ -517,6 +517,21 @@ int fused_cg_blocks_per_rhs(int nrhs, int max_blocks) {
     return (nrhs * 16 <= max_blocks) ? 16 : 8;
 }
 
+namespace {
+__global__ void k_fused_report_timeout(const uint32_t* err, CgState* cg, int nrhs) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= nrhs || __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) return;
+    cg[g].status = COLA_ERR_HIP;
+    cg[g].active = 0;
+    cg[g].need_update = 0;
+}
+}  // namespace
+
+hipError_t fused_cg_report_timeout(const uint32_t* err, CgState* cg, int nrhs, hipStream_t s) {
+    hipLaunchKernelGGL(k_fused_report_timeout, dim3((nrhs + 255) / 256), dim3(256), 0, s, err, cg, nrhs);
+    return hipGetLastError();
+}
+
 hipError_t launch_fused_cg(const FusedCgArgs& a, hipStream_t s) {
     if (a.nrhs < 1 || (a.bpr != 8 && a.bpr != 16)) return hipErrorInvalidValue;
     FusedCgArgs args = a;

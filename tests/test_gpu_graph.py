@@ -13,7 +13,7 @@ import workloads as wl
 pytestmark = pytest.mark.gpu
 
 
-def _capture_and_replay(systems, Bs, Ws, nrhs, prec, kw, replays=3):
+def _capture_and_replay(systems, Bs, Ws, nrhs, prec, kw, replays=3, check_eager=None):
     import torch
     from gpu_util import make_op, pack
     op = make_op(systems, prec=prec)
@@ -21,6 +21,8 @@ def _capture_and_replay(systems, Bs, Ws, nrhs, prec, kw, replays=3):
     G = pack(Ws)
     # eager reference (also sizes the workspace)
     X_e, _ = op.solve(B, nrhs, **kw)
+    if check_eager is not None:
+        check_eager(op, B, X_e)
     Lam_e, dfac_e, _, ds2_e, _ = op.solve_backward(X_e, G, nrhs, **kw)
     torch.cuda.synchronize()
     ref = (X_e.clone(), Lam_e.clone(), [t.clone() for s in dfac_e for row in s for t in row], ds2_e.clone())
@@ -56,3 +58,29 @@ def test_graph_replay_streaming_path_matches_eager():
 def test_graph_replay_uneven_batch_matches_eager():
     w = wl.config3(nsys=8, dmin=16, dmax=64, seed=72)
     _capture_and_replay(w.systems, w.B, w.W, 1, "fp32", dict(tol=1e-8, max_iters=2000, check_every=0))
+
+
+def test_graph_replay_fused_engine_matches_eager():
+    """64^3 RBF operator (the persistent fused CG's shape), FP32 with FP64 reliable updates,
+    check_every = 0: every 128-iteration cooperative launch and reliable-update tail is enqueued up
+    front, captured together with the backward and replayed bit-exactly.  The eager solve took the
+    fused engine (its launches counted) and equals, bit for bit, the host-checked solve with the same
+    128-iteration chunks."""
+    import torch
+    w = wl.config2(m=64, nrhs=2)
+    rng = np.random.default_rng(73)
+    Ws = [rng.standard_normal(w.B[0].shape)]
+    kw = dict(tol=1e-8, max_iters=300, check_every=0)
+
+    def fused_ran(op, B, X_e):
+        op.profile_enable(True)
+        X0, info0 = op.solve(B, 2, **kw)
+        torch.cuda.synchronize()
+        _, launches = op.profile_read("cg_fused")
+        op.profile_enable(False)
+        assert launches >= 3, launches                    # ceil(300 / 128) chunks
+        X1, _ = op.solve(B, 2, **dict(kw, check_every=128))
+        torch.cuda.synchronize()
+        assert torch.equal(X0, X_e) and torch.equal(X1, X_e)
+
+    _capture_and_replay(w.systems, w.B, Ws, 2, "fp32", kw, check_eager=fused_ran)
