@@ -230,13 +230,7 @@ int32_t enqueue_mvm(cola_op_s* op, const SysInfo& s, int prec, int nrhs, const v
         g.K1 = op->fac32 + s.fac_off[0];
         g.K2 = op->fac32 + s.fac_off[1];
         g.K3 = op->fac32 + s.fac_off[2];
-        if (prec == COLA_PREC_BF16X3) {      // the three BF16 planes of each factor
-            g.bf16x3 = 1;
-            g.K1b = op->facbf + s.fac_off[0];
-            g.K2b = op->facbf + s.fac_off[1];
-            g.K3b = op->facbf + s.fac_off[2];
-            g.plane = op->fac_elems;
-        }
+        g.bf16x3 = prec == COLA_PREC_BF16X3 ? 1 : 0;
         g.X = (const float*)X;
         g.R = (const float*)Rpnew;
         // the FP32 engine's direction pass also takes the deferred step x += alpha p_old; the BF16x3
@@ -257,8 +251,7 @@ int32_t enqueue_mvm(cola_op_s* op, const SysInfo& s, int prec, int nrhs, const v
         g.cnt = tmpl.cnt;
         auto al16 = [](const void* q) { return ((uintptr_t)q & 15) == 0; };
         const bool in_place_p = tmpl.epi != EPI_CG || tmpl.Epout == X;   // the direction is written over p_old
-        const bool planes_ok = !g.bf16x3 || (al16(g.K1b) && al16(g.K2b) && al16(g.K3b) && g.plane % 8 == 0);
-        if (in_place_p && planes_ok && al16(g.K1) && al16(g.K2) && al16(g.K3) && al16(g.X) && al16(g.R) &&
+        if (in_place_p && al16(g.K1) && al16(g.K2) && al16(g.K3) && al16(g.X) && al16(g.R) &&
             al16(g.Xit) && al16(g.Y) && al16(g.dvec)) {
             const char* names[3] = {"gemm_mode3", "gemm_mode2", "gemm_mode1"};
             for (int m = 3; m >= 1; --m) {

@@ -13,10 +13,8 @@ namespace cola {
 //   pass 1: q [r][a'][b'][c'] = sum_a Z2[r][b'][c'][a] K1[a', a] (+ diagonal; CG epilogue)
 struct Gemm3Args {
     int32_t n1, n2, n3, nrhs;
-    int32_t bf16x3;           // 0: FP32 factors K1..K3 on FP32 MFMA; 1: the BF16x3 splits K1b..K3b
-    const float* K1; const float* K2; const float* K3;
-    const __bf16* K1b; const __bf16* K2b; const __bf16* K3b;   // BF16x3: hi plane of each factor
-    int64_t plane;            // BF16x3: elements between the hi, mid and lo planes
+    int32_t bf16x3;           // 0: FP32 MFMA; 1: BF16x3 (both operands split three ways when staged)
+    const float* K1; const float* K2; const float* K3;   // FP32 working copies of the factors
     const float* X;           // CG: p_old (p_new is written back in place); matvec: x
     const float* R;           // CG: r
     float* Xit;               // CG with reliable updates: the iterate; the first pass applies the

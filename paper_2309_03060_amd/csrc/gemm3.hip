@@ -50,8 +50,6 @@ struct PassDesc {
     const float* R;        // PNEW: residual, same layout as A
     float* Pout;           // PNEW: the direction, written back (aliases A)
     const float* B;        // N x K factor, row-major
-    const __bf16* Bb;      // BF16x3: hi plane of the factor (mid and lo `plane` elements further)
-    int64_t plane;
     float* Out;
     int64_t rows_per_rhs;
     int32_t K, N;
@@ -244,7 +242,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm3(Gemm3Args a, PassDesc d) {
 // BF16x3 working precision: the same three passes on the BF16 matrix cores.
 // Every FP32 operand v is split into three BF16 parts while it is staged,
 // v = h + m + l (each part the round-to-nearest-even BF16 of the remainder),
-// and the factors come pre-split the same way in three planes.  Each k step
+// the factor (FP32 working copy) the same way.  Each k step
 // forms the six leading cross products hh, hm, mh, hl, lh and mm with
 // v_mfma_f32_32x32x16_bf16 into one FP32 accumulator; the dropped products
 // (ml, lm, ll) are below FP32 rounding, so the pass matches the FP32 engine's
@@ -258,8 +256,8 @@ __global__ __launch_bounds__(kThreads) void k_gemm3(Gemm3Args a, PassDesc d) {
 // Block tile 256 (factor rows n) x 256 (vector rows m), 8 waves (two per
 // SIMD) of 128 x 64 (4 x 2 MFMA tiles), k slice 16 (one MFMA step per
 // product).  The vector operand of a slice (from HBM) is loaded into
-// registers two slices ahead (two register sets), the factor planes (from L2)
-// one slice ahead, and both are written to one of two LDS stages one slice
+// registers two slices ahead (two register sets), the factor (from L2)
+// one slice ahead, and both are split into one of two LDS stages one slice
 // ahead, so every wait is on a register the compiler tracks exactly.  A stage
 // holds six planes of 256 rows x 32 bytes (vector hi/mid/lo, factor
 // hi/mid/lo); 16-byte chunk p of row rho holds k chunk p ^ sw(rho) with
@@ -312,10 +310,12 @@ struct OpSet {
     floatx4 r[PNEW ? 2 : 1];
 };
 
-// The same thread's 8 values of each factor plane (from L2): loaded at the start of the step
-// that stores them (one register set).
+// The same thread's 8 values of the factor (FP32, from L2), split like the vector operand
+// when staged: loaded at the start of the step that stores them (one register set).  Two
+// 16-byte loads instead of three pre-split planes: a third less L1 traffic for the factor,
+// and fewer registers held across the step.
 struct FacSet {
-    bf16x8 f[3];
+    floatx4 f[2];
 };
 
 // The direction pass (PNEW) leaves x += alpha p to the vector update: taking that step here
@@ -325,8 +325,7 @@ struct X3Thread {
     const float* A;      // this thread's vector row, at its k chunk
     const float* R;      // PNEW: residual
     float* P;            // PNEW: direction written back
-    const __bf16* F;     // this thread's factor row (hi plane), at its k chunk
-    int64_t plane;
+    const float* F;      // this thread's factor row (FP32), at its k chunk
     double beta;
     uint32_t sdst;       // byte offset of this thread's chunk in a plane
     uint32_t afr, bfr;   // fragment offsets (factor tile 0, vector tile 0)
@@ -339,8 +338,8 @@ struct X3Thread {
         }
     }
     __device__ __attribute__((always_inline)) void load_fac(int k0, FacSet& fs) const {
-#pragma unroll
-        for (int s = 0; s < 3; ++s) fs.f[s] = *(const bf16x8*)(F + s * plane + k0);
+        fs.f[0] = *(const floatx4*)(F + k0);
+        fs.f[1] = *(const floatx4*)(F + k0 + 4);
     }
     // the direction is formed here, once per element (the direction pass has one N tile),
     // written back in place of p_old, then split into the stage
@@ -360,8 +359,10 @@ struct X3Thread {
         *(bf16x8*)(stage + sdst) = hp;
         *(bf16x8*)(stage + XPLANE + sdst) = mp;
         *(bf16x8*)(stage + 2 * XPLANE + sdst) = lp;
-#pragma unroll
-        for (int s = 0; s < 3; ++s) *(bf16x8*)(stage + (3 + s) * XPLANE + sdst) = fs.f[s];
+        split3(fs.f[0], fs.f[1], hp, mp, lp);
+        *(bf16x8*)(stage + 3 * XPLANE + sdst) = hp;
+        *(bf16x8*)(stage + 4 * XPLANE + sdst) = mp;
+        *(bf16x8*)(stage + 5 * XPLANE + sdst) = lp;
     }
     // acc[i][j] += factor tile i x vector tile j over the slice: factor part outer, so only
     // one factor part's fragments are live at a time
@@ -423,8 +424,7 @@ __global__ __launch_bounds__(XT) void k_gemm3x3(Gemm3Args a, PassDesc d) {
     th.A = d.A + sofs;
     th.R = PNEW ? d.R + sofs : nullptr;
     th.P = PNEW ? d.Pout + sofs : nullptr;
-    th.F = d.Bb + (int64_t)(n0 + srow) * K + 8 * schunk;
-    th.plane = d.plane;
+    th.F = d.B + (int64_t)(n0 + srow) * K + 8 * schunk;
     th.beta = PNEW ? a.cg[r].beta : 0.0;
     th.sdst = (uint32_t)(srow * XROW + 16 * (schunk ^ x3_swz(srow)));
     // fragment reads: row (lane % 32) of each 32-row tile, logical chunk lane / 32
@@ -545,22 +545,20 @@ hipError_t launch_gemm3(const Gemm3Args& a, int mode, hipStream_t s) {
     if (!gemm3_supported(COLA_PREC_FP32, 3, 1, dims) || a.nrhs < 1) return hipErrorInvalidValue;
     const bool cg = a.epi == EPI_CG;
     if (cg && (!a.R || !a.cg || !a.partials || !a.counters)) return hipErrorInvalidValue;
-    if (a.bf16x3 && (!a.K1b || !a.K2b || !a.K3b || a.plane <= 0)) return hipErrorInvalidValue;
     PassDesc d;
     std::memset(&d, 0, sizeof(d));
     if (mode == 3) {
-        d.A = a.X; d.R = a.R; d.Pout = const_cast<float*>(a.X); d.B = a.K3; d.Bb = a.K3b; d.Out = a.Z1;
+        d.A = a.X; d.R = a.R; d.Pout = const_cast<float*>(a.X); d.B = a.K3; d.Out = a.Z1;
         d.rows_per_rhs = (int64_t)a.n1 * a.n2; d.K = a.n3; d.N = a.n3;
     } else if (mode == 2) {
-        d.A = a.Z1; d.B = a.K2; d.Bb = a.K2b; d.Out = a.Z2;
+        d.A = a.Z1; d.B = a.K2; d.Out = a.Z2;
         d.rows_per_rhs = (int64_t)a.n3 * a.n1; d.K = a.n2; d.N = a.n2;
     } else if (mode == 1) {
-        d.A = a.Z2; d.B = a.K1; d.Bb = a.K1b; d.Out = a.Y;
+        d.A = a.Z2; d.B = a.K1; d.Out = a.Y;
         d.rows_per_rhs = (int64_t)a.n2 * a.n3; d.K = a.n1; d.N = a.n1;
     } else {
         return hipErrorInvalidValue;
     }
-    d.plane = a.plane;
     const int64_t T = (int64_t)a.nrhs * d.rows_per_rhs / BM * (d.N / BN);
     if (a.bf16x3) {
         const dim3 grid((unsigned)T), block(XT);
