@@ -339,6 +339,9 @@ int32_t cola_autotune(cola_op_t op, int32_t nrhs, void* stream);
 #define COLA_ENGINE_RESIDENT 5  /* resident batched CG of many small two-mode systems           */
 #define COLA_ENGINE_SMALL64  6  /* FP64 solves of one-term two-mode systems with modes <= 64: the
                                    whole CG of each (system, RHS) in one workgroup (no precond) */
+#define COLA_ENGINE_GEMM64   7  /* FP64 passes (residuals of mixed precision, FP64 CG, FP64
+                                   products) of two-mode operators with modes multiples of 256
+                                   as two dense FP64 GEMMs                                    */
 int32_t cola_op_set_engine(cola_op_t op, int32_t engine, int32_t enable);
 
 /* Per-kernel timing with HIP events recorded on the launch stream around
@@ -347,8 +350,9 @@ int32_t cola_op_set_engine(cola_op_t op, int32_t engine, int32_t enable);
  * mode), "contract_last" (first mode, with the diagonal term and the CG
  * epilogue), "update" (x, r update and residual norm), "resident" (batched
  * small systems), "cg_fused" (one launch of the persistent CG: a chunk of
- * iterations for a batch of right-hand sides); the same names with "_fp64" for launches in FP64 (plain
- * FP64 solves and the FP64 residuals of mixed precision).  enable != 0
+ * iterations for a batch of right-hand sides), "gemm_pack", "gemm_mode3",
+ * "gemm_mode2", "gemm_mode1" (the dense-GEMM engines' passes); the same names with "_fp64" for
+ * launches in FP64 (plain FP64 solves and the FP64 residuals of mixed precision).  enable != 0
  * starts collecting (and clears totals). */
 int32_t cola_profile_enable(cola_op_t op, int32_t enable);
 /* Totals since enable: summed milliseconds and launch count for `kernel`;

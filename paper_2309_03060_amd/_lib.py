@@ -34,7 +34,7 @@ COLA_REFINE_RELIABLE = 0
 COLA_REFINE_RESTART = 1
 REFINE_BY_NAME = {"reliable": COLA_REFINE_RELIABLE, "restart": COLA_REFINE_RESTART}
 
-ENGINE_BY_NAME = {"fused_cg": 1, "gemm2": 2, "gemm3": 3, "slab": 4, "resident": 5, "small64": 6}
+ENGINE_BY_NAME = {"fused_cg": 1, "gemm2": 2, "gemm3": 3, "slab": 4, "resident": 5, "small64": 6, "gemm64": 7}
 PRECOND_BY_NAME = {"none": 0, "jacobi": 1, "kron_eig": 2}
 DIAG_MODE_BY_NAME = {"hutchinson": 0, "doubly": 1}
 

@@ -175,6 +175,56 @@ int32_t enqueue_mvm(cola_op_s* op, const SysInfo& s, int prec, int nrhs, const v
     if (s.diag_off >= 0)
         diag = (prec == COLA_PREC_FP64) ? (const void*)(op->diag64 + s.diag_off)
                                         : (const void*)(op->diag32 + s.diag_off);
+    if (prec == COLA_PREC_FP64 && op->use_gemm64 && tmpl.epi != EPI_STORE && !tmpl.Ex &&
+        gemm64_supported(s.Fv, s.dims) &&
+        (tmpl.epi == EPI_MATVEC || gemm64_blocks_per_rhs(s.dims[0], s.dims[1]) <= tmpl.part_stride)) {
+        // large two-mode operator in FP64 (residuals, FP64 CG, products): two dense FP64 GEMMs
+        Gemm64Args g;
+        std::memset(&g, 0, sizeof(g));
+        g.n1 = (int32_t)s.dims[0];
+        g.n2 = (int32_t)s.dims[1];
+        g.J = s.J;
+        g.nrhs = nrhs;
+        g.U = op->fac64 + s.fac_off[0];
+        g.V = op->fac64 + s.fac_off[1];
+        const bool cg = tmpl.epi == EPI_CG;
+        g.Pold = cg ? (const double*)X : nullptr;
+        g.R = cg ? (const double*)Rpnew : nullptr;
+        g.P = cg ? (double*)tmpl.Epout : nullptr;
+        g.X = cg ? g.P : (const double*)X;
+        g.Ep = cg ? g.P : (const double*)tmpl.Ep;
+        g.Er = (const double*)tmpl.Er;
+        g.T = (double*)inter[0];
+        g.Y = (double*)Yout;
+        g.dvec = (const double*)diag;
+        g.sigma2 = s.sigma2;
+        g.epi = tmpl.epi;
+        g.cg = tmpl.cg;
+        g.outer = tmpl.outer;
+        g.gate = tmpl.gate;
+        g.gate_stride = tmpl.gate_stride;
+        g.partials = tmpl.partials;
+        g.part_stride = tmpl.part_stride;
+        g.counters = tmpl.counters;
+        g.cnt = tmpl.cnt;
+        auto al16 = [](const void* q) { return ((uintptr_t)q & 15) == 0; };
+        if (al16(g.U) && al16(g.V) && al16(g.X) && al16(g.R) && al16(g.Pold) && al16(g.P) && al16(g.T) &&
+            al16(g.Y) && al16(g.Ep) && al16(g.Er) && al16(g.dvec)) {
+            if (cg) {
+                ProfScope ps(prof, "gemm_pack_fp64", st);
+                HIP_TRY(launch_gemm64(g, 0, st));
+            }
+            {
+                ProfScope ps(prof, "gemm_mode2_fp64", st);
+                HIP_TRY(launch_gemm64(g, 1, st));
+            }
+            {
+                ProfScope ps(prof, "gemm_mode1_fp64", st);
+                HIP_TRY(launch_gemm64(g, 2, st));
+            }
+            return COLA_OK;
+        }
+    }
     if (op->use_gemm2 && (tmpl.epi == EPI_CG || tmpl.epi == EPI_MATVEC) && gemm2_supported(prec, s.Fv, s.dims)) {
         // large two-mode operator in BF16: both mode products as dense GEMMs
         Gemm2Args g;
@@ -1708,6 +1758,7 @@ int32_t cola_op_set_engine(cola_op_t op, int32_t engine, int32_t enable) {
         case COLA_ENGINE_SLAB: op->use_slab = on; break;
         case COLA_ENGINE_RESIDENT: op->use_resident = on; break;
         case COLA_ENGINE_SMALL64: op->use_small = on; break;
+        case COLA_ENGINE_GEMM64: op->use_gemm64 = on; break;
         default: return COLA_ERR_INVALID_ARG;
     }
     (void)hipDeviceSynchronize();

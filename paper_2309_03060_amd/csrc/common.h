@@ -178,6 +178,32 @@ __device__ inline void record_residual(const ResHist& h, int64_t g, const CgStat
     h.data[g * h.len + k] = st.bnorm2 > 0.0 ? sqrt(rho / st.bnorm2) : sqrt(rho);
 }
 
+__device__ inline bool finite_d(double v) { return __builtin_isfinite(v); }
+
+// Restarted refinement, after the FP64 residual of a sweep (||b - A x||^2 = tot): record it and
+// decide the right-hand side's fate (converged, stagnated, out of sweeps, or refine again).
+// Runs in one thread per right-hand side.
+__device__ inline void outer_residual(OuterState& o, double tot, SolveCounters* cnt) {
+    const double rn = sqrt(tot);
+    const double bn = sqrt(o.bnorm2);
+    o.rnorm = rn;
+    o.relres = bn > 0.0 ? rn / bn : rn;
+    int status = -100;   // still refining
+    if (!finite_d(rn)) status = COLA_ERR_NONFINITE;
+    else if (o.relres <= o.tol) status = COLA_OK;
+    else {
+        o.slow = (rn > 0.5 * o.prev_rnorm) ? o.slow + 1 : 0;
+        if (o.slow >= 2) status = COLA_STAGNATED;
+        else if (o.sweeps >= o.max_sweeps) status = COLA_NOT_CONVERGED;
+    }
+    o.prev_rnorm = rn;
+    if (status != -100) {
+        o.status = status;
+        o.active = 0;
+        atomicSub(&cnt->num_outer_active, 1);
+    }
+}
+
 // After a reliable update has put ||b - A x||^2 into st.rho_true (x already
 // holds the folded FP64 solution and r the replaced residual): decide
 // convergence from the true residual, resume a paused right-hand side, and
@@ -220,7 +246,6 @@ __device__ inline void reliable_finish(CgState& st, SolveCounters* cnt) {
 __device__ inline int acc_row(float, int lane, int v)  { return 4 * (lane >> 4) + v; }
 __device__ inline int acc_row(double, int lane, int v) { return 4 * v + (lane >> 4); }
 
-__device__ inline bool finite_d(double v) { return __builtin_isfinite(v); }
 
 // p_new = r + beta * p_old, evaluated identically wherever it is needed so
 // that every kernel of an iteration sees the same rounded direction.

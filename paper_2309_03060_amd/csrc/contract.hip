@@ -545,25 +545,7 @@ __global__ __launch_bounds__(kThreads) void k_contract(PassArgs a) {
                 } else if (a.epi == EPI_RESID_CG) {
                     a.cg[g].rho_true = tot;
                 } else {
-                    OuterState& o = a.outer[g];
-                    const double rn = sqrt(tot);
-                    const double bn = sqrt(o.bnorm2);
-                    o.rnorm = rn;
-                    o.relres = bn > 0.0 ? rn / bn : rn;
-                    int status = -100;   // still refining
-                    if (!finite_d(rn)) status = COLA_ERR_NONFINITE;
-                    else if (o.relres <= o.tol) status = COLA_OK;
-                    else {
-                        o.slow = (rn > 0.5 * o.prev_rnorm) ? o.slow + 1 : 0;
-                        if (o.slow >= 2) status = COLA_STAGNATED;
-                        else if (o.sweeps >= o.max_sweeps) status = COLA_NOT_CONVERGED;
-                    }
-                    o.prev_rnorm = rn;
-                    if (status != -100) {
-                        o.status = status;
-                        o.active = 0;
-                        atomicSub(&a.cnt->num_outer_active, 1);
-                    }
+                    outer_residual(a.outer[g], tot, a.cnt);
                 }
             }
         }

@@ -40,4 +40,45 @@ hipError_t launch_gemm2(const Gemm2Args& a, int stage, hipStream_t s);
 // Blocks per right-hand side of G2 (reduction partials needed).
 int64_t gemm2_blocks_per_rhs(int64_t n1, int64_t n2);
 
+// The same two GEMMs in FP64 (v_mfma_f64_16x16x4f64) with the FP64 master
+// factors, for the FP64 passes of two-mode operators whose modes are
+// multiples of 256: the residuals b - A x of mixed-precision solves, FP64 CG
+// and FP64 products.
+//   pack (CG): p = r + beta p_old, written in place of p_old
+//   G1: T_r[b][(j, a')] = sum_b' X[(r, a'), b'] V_j[b, b']
+//   G2: y_r[a, b] = sum_(j, a') U_j[a, a'] T_r[b][(j, a')], then the epilogue
+//       (EPI_MATVEC: y + (sigma2 + d) x; EPI_CG: q = y + (sigma2 + d) p, p.q and
+//       the step length; EPI_RESID / EPI_RESID_CG: b - (y + (sigma2 + d) x) and
+//       its squared norm).
+struct Gemm64Args {
+    int32_t n1, n2, J, nrhs;
+    const double* U;          // term j's mode-1 factor at U + j * n1 * n1
+    const double* V;          // term j's mode-2 factor at V + j * n2 * n2
+    const double* X;          // G1 operand: x, or p (CG, after the pack pass)
+    const double* R;          // CG: r
+    const double* Pold;       // CG: p_old
+    double* P;                // CG: p_new (may alias Pold)
+    double* T;                // nrhs * n2 * J * n1
+    double* Y;                // output
+    const double* Ep;         // epilogue operand: x, or p_new (CG)
+    const double* Er;         // residual epilogues: b
+    const double* dvec;       // n1 * n2 or null
+    double sigma2;
+    int32_t epi;
+    CgState* cg;
+    OuterState* outer;
+    const int32_t* gate; int32_t gate_stride;
+    double* partials; int32_t part_stride;
+    uint32_t* counters;
+    SolveCounters* cnt;
+};
+
+bool gemm64_supported(int Fv, const int64_t* dims);
+
+// `stage` 0 = pack (CG only), 1 = G1, 2 = G2.
+hipError_t launch_gemm64(const Gemm64Args& a, int stage, hipStream_t s);
+
+// Blocks per right-hand side of the FP64 G2.
+int64_t gemm64_blocks_per_rhs(int64_t n1, int64_t n2);
+
 }  // namespace cola

@@ -330,6 +330,233 @@ __global__ __launch_bounds__(kGT) void k_gemm2_y(Gemm2Args a) {
     }
 }
 
+
+// ---------------------------------------------------------------------------
+// FP64 engine.  Block tile 256 (A rows) x 128 (B rows), k slice 16, 8 waves
+// (two per SIMD) each owning 64 x 64 (4 x 4 tiles of v_mfma_f64_16x16x4f64,
+// whose A operand lane l holds row l % 16, k l / 16, and whose accumulator
+// element v of lane l is row 4 v + l / 16, column l % 16).  Slices move from
+// global memory straight into one of two LDS stages (global_load_lds_dwordx4)
+// one slice ahead of the one being multiplied.  LDS rows are 128 bytes (A rows
+// 0..255, then B rows 256..383); 16-byte chunk c of row rho sits at chunk
+// c ^ h(rho), h(rho) = (rho / 2) % 8, which puts the 32 lanes of each half of a
+// fragment read (16 rows, two k) on 64 distinct banks.
+
+constexpr int DM = 256, DN = 128, DKS = 16;
+constexpr int kDStage = (DM + DN) * DKS * 8;          // bytes of one stage (48 KiB)
+
+__device__ inline doublex4 mfma64(double a, double b, doublex4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Issue the copies of one k slice: A rows from ga (row stride lda), B rows from
+// gb (stride ldb), into stage N.  Wave w copies row blocks 8 q + w of 8 rows.
+__device__ __attribute__((always_inline)) inline void g64_issue(char* __restrict__ N, const double* ga, int64_t lda,
+                                                               const double* gb, int64_t ldb, int64_t aoff,
+                                                               int64_t boff, int wave) {
+#pragma unroll
+    for (int q = 0; q < DM / 64; ++q) {
+        const int rb = 8 * q + wave;
+        __builtin_amdgcn_global_load_lds((const void*)(ga + (int64_t)rb * 8 * lda + aoff),
+                                         (__attribute__((address_space(3))) void*)(N + rb * 8 * 128), 16, 0, 0);
+    }
+#pragma unroll
+    for (int q = 0; q < DN / 64; ++q) {
+        const int rb = 8 * q + wave;
+        __builtin_amdgcn_global_load_lds((const void*)(gb + (int64_t)rb * 8 * ldb + boff),
+                                         (__attribute__((address_space(3))) void*)(N + (DM + rb * 8) * 128), 16, 0,
+                                         0);
+    }
+}
+
+__device__ __attribute__((always_inline)) inline void g64_step(doublex4 (&acc)[4][4], const char* __restrict__ S,
+                                                              char* __restrict__ N, bool more, const double* ga,
+                                                              int64_t lda, const double* gb, int64_t ldb,
+                                                              int64_t aoff, int64_t boff, int wave,
+                                                              const uint32_t (&fo)[4], uint32_t abyte,
+                                                              uint32_t bbyte) {
+    if (more) g64_issue(N, ga, lda, gb, ldb, aoff, boff, wave);
+#pragma unroll
+    for (int m = 0; m < DKS / 4; ++m) {
+        double av[4], bv[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) av[i] = *(const double*)(S + abyte + i * 16 * 128 + fo[m]);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) bv[j] = *(const double*)(S + bbyte + j * 16 * 128 + fo[m]);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] = mfma64(av[i], bv[j], acc[i][j]);
+    }
+}
+
+// acc += A_tile * B_tile^T over k in [0, nk): abase(k0) / bbase(k0) give row 0, column k0 of
+// the A / B tile (rows lda / ldb elements apart, 16-byte aligned).
+template <class ABase, class BBase>
+__device__ inline void gemm64_tile(doublex4 (&acc)[4][4], int nk, ABase abase, int64_t lda, BBase bbase,
+                                   int64_t ldb, char* smem) {
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) & 7;   // scalar, range known
+    const int wa = wave >> 1, wb = wave & 1;
+    // copies: lane l fills row rb*8 + l/8, physical chunk l % 8, i.e. logical chunk (l % 8) ^ h with
+    // h = 4 (rb % 2) + l / 16 = 4 (w % 2) + l / 16 for this wave's row blocks
+    const int lc = (lane & 7) ^ (4 * (wave & 1) + (lane >> 4));
+    const int64_t aoff = (int64_t)(lane >> 3) * lda + 2 * lc;
+    const int64_t boff = (int64_t)(lane >> 3) * ldb + 2 * lc;
+    // fragment reads: row (tile base) + l % 16, k = 4 m + l / 16 -> logical chunk 2 m + l / 32,
+    // double (l / 16) % 2; h = (l % 16) / 2 for every 16-row tile
+    uint32_t fo[4];
+    const int fr = lane & 15;
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+        fo[m] = (uint32_t)(fr * 128 + 16 * ((2 * m + (lane >> 5)) ^ (fr >> 1)) + 8 * ((lane >> 4) & 1));
+    const uint32_t abyte = (uint32_t)(wa * 64 * 128), bbyte = (uint32_t)((DM + wb * 64) * 128);
+    g64_issue(smem, abase(0), lda, bbase(0), ldb, aoff, boff, wave);
+    char* cur = smem;
+    char* nxt = smem + kDStage;
+    for (int k0 = 0; k0 < nk; k0 += DKS) {
+        __builtin_amdgcn_s_waitcnt(0xF70);                 // vmcnt(0): this wave's part of slice k0 is in LDS
+        __syncthreads();                                   // all of it; the other stage no longer read
+        const bool more = k0 + DKS < nk;
+        const int kn = more ? k0 + DKS : k0;
+        g64_step(acc, cur, nxt, more, abase(kn), lda, bbase(kn), ldb, aoff, boff, wave, fo, abyte, bbyte);
+        char* t = cur;
+        cur = nxt;
+        nxt = t;
+    }
+}
+
+__device__ inline bool g64_active(const Gemm64Args& a, int r) {
+    return a.gate ? a.gate[(int64_t)r * a.gate_stride] != 0 : true;
+}
+
+__global__ __launch_bounds__(kThreads) void k_gemm64_pack(Gemm64Args a) {
+    const int r = blockIdx.y;
+    if (!g64_active(a, r)) return;
+    const int64_t n = (int64_t)a.n1 * a.n2;
+    const double beta = a.cg[r].beta;
+    const double* Xo = a.Pold + (int64_t)r * n;
+    const double* R = a.R + (int64_t)r * n;
+    double* P = a.P + (int64_t)r * n;
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n / 2; i += (int64_t)gridDim.x * kThreads) {
+        const d2 x = ((const d2*)Xo)[i], rr = ((const d2*)R)[i];
+        ((d2*)P)[i] = d2{pnew_of(rr[0], x[0], beta), pnew_of(rr[1], x[1], beta)};
+    }
+}
+
+// G1: A = rows of [V_1; ..; V_J] (256 per tile, one term), B = rows of X (128 per tile, one
+// right-hand side); the accumulator tile is T_r[b][(j, a')] with a' along the lanes.
+__global__ __launch_bounds__(kGT) void k_gemm64_t(Gemm64Args a) {
+    __shared__ __attribute__((aligned(16))) char smem[2 * kDStage];
+    const int Mt = a.J * a.n2 / DM, Nt = a.nrhs * a.n1 / DN;
+    const int L = xcd_linear(blockIdx.x, Mt * Nt);
+    const int mt = L % Mt, nt = L / Mt;                    // the A panels of all terms cycle fastest
+    const int64_t m0 = (int64_t)mt * DM, n0 = (int64_t)nt * DN;
+    const int r = (int)(n0 / a.n1);
+    if (!g64_active(a, r)) return;
+    const int64_t n2 = a.n2;
+    const double* Ab = a.V + m0 * n2;                      // rows (j, b) of the stacked factors
+    const double* Bb = a.X + n0 * n2;                      // rows (r, a') of X
+    doublex4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = doublex4{0.0, 0.0, 0.0, 0.0};
+    gemm64_tile(acc, a.n2, [&](int k0) { return Ab + k0; }, n2, [&](int k0) { return Bb + k0; }, n2, smem);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, wa = wave >> 1, wb = wave & 1;
+    const int64_t ldt = (int64_t)a.J * a.n1;
+    const int jt = (int)(m0 / n2);
+    const int64_t b_lane = m0 - (int64_t)jt * n2 + wa * 64 + (lane >> 4);
+    const int64_t a_lane = n0 - (int64_t)r * a.n1 + wb * 64 + (lane & 15);
+    double* const out = a.T + ((int64_t)r * n2 + b_lane) * ldt + (int64_t)jt * a.n1 + a_lane;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) out[(int64_t)(16 * i + 4 * v) * ldt + 16 * j] = acc[i][j][v];
+}
+
+// G2: A = rows a of [U_1 .. U_J] (k = (j, a')), B = rows b of T_r; the accumulator tile is
+// y_r[a][b] with b along the lanes, followed by the epilogue.
+__global__ __launch_bounds__(kGT) void k_gemm64_y(Gemm64Args a) {
+    __shared__ __attribute__((aligned(16))) char smem[2 * kDStage];
+    __shared__ double red[8];
+    const int tn = a.n2 / DN, tpr = (a.n1 / DM) * tn;
+    const int L = xcd_linear(blockIdx.x, a.nrhs * tpr);
+    const int r = L / tpr, t = L % tpr;
+    if (!g64_active(a, r)) return;
+    const int a0 = (t / tn) * DM, b0 = (t % tn) * DN;
+    const int64_t n1 = a.n1, n2 = a.n2, ldt = (int64_t)a.J * a.n1;
+    const double* Tr = a.T + ((int64_t)r * n2 + b0) * ldt;
+    doublex4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = doublex4{0.0, 0.0, 0.0, 0.0};
+    gemm64_tile(acc, (int)ldt,
+                [&](int k0) {
+                    const int64_t j = k0 / n1;             // a 16-wide k slice never spans two terms
+                    return a.U + j * n1 * n1 + a0 * n1 + (k0 - j * n1);
+                },
+                n1, [&](int k0) { return Tr + k0; }, ldt, smem);
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, wa = wave >> 1, wb = wave & 1;
+    const int64_t n = n1 * n2;
+    const int64_t e_lane = (int64_t)(a0 + wa * 64 + (lane >> 4)) * n2 + b0 + wb * 64 + (lane & 15);
+    const int64_t g_lane = (int64_t)r * n + e_lane;
+    const int epi = a.epi;
+    const double s2 = a.sigma2;
+    double dot = 0.0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            double xv[4], bv[4], dv[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t o = (int64_t)(16 * i + 4 * v) * n2 + 16 * j;
+                xv[v] = epi != EPI_STORE ? a.Ep[g_lane + o] : 0.0;
+                bv[v] = (epi == EPI_RESID || epi == EPI_RESID_CG) ? a.Er[g_lane + o] : 0.0;
+                dv[v] = a.dvec ? a.dvec[e_lane + o] : 0.0;
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t o = (int64_t)(16 * i + 4 * v) * n2 + 16 * j;
+                double y = acc[i][j][v];
+                if (epi != EPI_STORE) y = __builtin_fma(s2 + dv[v], xv[v], y);
+                if (epi == EPI_CG) {
+                    dot = __builtin_fma(xv[v], y, dot);
+                } else if (epi == EPI_RESID || epi == EPI_RESID_CG) {
+                    y = bv[v] - y;
+                    dot = __builtin_fma(y, y, dot);
+                }
+                a.Y[g_lane + o] = y;
+            }
+        }
+    if (epi != EPI_CG && epi != EPI_RESID && epi != EPI_RESID_CG) return;
+    const double s = block_sum8(dot, red);
+    double tot;
+    if (last_block_reduce8(s, a.partials + (int64_t)r * a.part_stride, a.counters + r, tpr, t, &tot, red) &&
+        threadIdx.x == 0) {
+        if (epi == EPI_CG) {
+            CgState& st = a.cg[r];
+            if (!(tot > 0.0) || !finite_d(tot)) {
+                st.status = finite_d(tot) ? COLA_ERR_NOT_SPD : COLA_ERR_NONFINITE;
+                st.active = 0;
+                atomicSub(&a.cnt->num_active, 1);
+            } else {
+                st.alpha = st.rho / tot;
+            }
+        } else if (epi == EPI_RESID_CG) {
+            a.cg[r].rho_true = tot;
+        } else {
+            outer_residual(a.outer[r], tot, a.cnt);
+        }
+    }
+}
+
 }  // namespace
 
 bool gemm2_supported(int prec, int Fv, const int64_t* dims) {
@@ -338,6 +565,35 @@ bool gemm2_supported(int prec, int Fv, const int64_t* dims) {
 }
 
 int64_t gemm2_blocks_per_rhs(int64_t n1, int64_t n2) { return (n1 / BM) * (n2 / BN); }
+
+bool gemm64_supported(int Fv, const int64_t* dims) {
+    return Fv == 2 && dims[0] >= DM && dims[1] >= DM && dims[0] % DM == 0 && dims[1] % DM == 0;
+}
+
+int64_t gemm64_blocks_per_rhs(int64_t n1, int64_t n2) { return (n1 / DM) * (n2 / DN); }
+
+hipError_t launch_gemm64(const Gemm64Args& a, int stage, hipStream_t s) {
+    const int64_t dims[2] = {a.n1, a.n2};
+    if (!gemm64_supported(2, dims) || a.nrhs < 1 || a.J < 1) return hipErrorInvalidValue;
+    const bool cg = a.epi == EPI_CG;
+    const bool resid = a.epi == EPI_RESID || a.epi == EPI_RESID_CG;
+    if ((cg && (!a.R || !a.P || !a.Pold || !a.cg)) || (resid && !a.Er) || (a.epi == EPI_RESID && !a.outer) ||
+        (a.epi == EPI_RESID_CG && !a.cg) || (a.epi != EPI_STORE && !a.Ep))
+        return hipErrorInvalidValue;
+    if (stage == 0) {
+        if (!cg) return hipSuccess;
+        const int64_t n2h = (int64_t)a.n1 * a.n2 / 2;
+        const int64_t bx = std::min<int64_t>(512, (n2h + kThreads - 1) / kThreads);
+        hipLaunchKernelGGL(k_gemm64_pack, dim3((unsigned)bx, (unsigned)a.nrhs), dim3(kThreads), 0, s, a);
+    } else if (stage == 1) {
+        const int64_t T = (int64_t)(a.J * a.n2 / DM) * (a.nrhs * (int64_t)a.n1 / DN);
+        hipLaunchKernelGGL(k_gemm64_t, dim3((unsigned)T), dim3(kGT), 0, s, a);
+    } else {
+        const int64_t T = (int64_t)a.nrhs * gemm64_blocks_per_rhs(a.n1, a.n2);
+        hipLaunchKernelGGL(k_gemm64_y, dim3((unsigned)T), dim3(kGT), 0, s, a);
+    }
+    return hipGetLastError();
+}
 
 hipError_t launch_gemm2(const Gemm2Args& a, int stage, hipStream_t s) {
     if (a.n1 % BM || a.n2 % BN || a.n1 < BM || a.n2 < BN || a.nrhs < 1 || a.J < 1) return hipErrorInvalidValue;

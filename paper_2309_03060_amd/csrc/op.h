@@ -126,6 +126,7 @@ struct cola_op_s {
     bool use_slab = true;           // fuse modes 2 and 3 of three-mode terms when slabs fit in LDS
     bool use_gemm2 = true;          // BF16 two-mode operators with large modes: dense-GEMM MVM
     bool use_gemm3 = true;          // FP32 one-term three-mode operators with 256-wide modes: dense-GEMM MVM
+    bool use_gemm64 = true;         // FP64 passes of two-mode operators with modes multiples of 256: dense FP64 GEMMs
     bool use_fused = true;          // FP32 one-term three-mode operators with 64-wide modes: persistent fused CG
     int fused_max_blocks = -1;      // co-resident fused-CG blocks (-1: not yet queried)
     double* slq_buf = nullptr;      // SLQ: CG coefficient history and per-probe estimates

@@ -169,7 +169,7 @@ template <typename T>
 __global__ __launch_bounds__(kThreads) void k_cg_update(T* x, T* r, const T* p, const T* q, int64_t n,
                                                         CgState* cg, double* partials, int part_stride,
                                                         uint32_t* counters, SolveCounters* cnt, double* hist,
-                                                        int hist_len, ResHist rh) {
+                                                        int hist_len, ResHist rh, int streaming) {
     __shared__ double red[4];
     const int64_t g = blockIdx.y;
     if (!cg[g].active) return;
@@ -196,7 +196,22 @@ __global__ __launch_bounds__(kThreads) void k_cg_update(T* x, T* r, const T* p, 
             ((VT*)rg)[i] = rv;
         }
     }
-    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; !defer && i < nv; i += stride) {
+    if (streaming) {                                    // working set beyond the last-level cache
+        for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; !defer && i < nv; i += stride) {
+            VT xv = __builtin_nontemporal_load((VT*)xg + i), rv = __builtin_nontemporal_load((VT*)rg + i);
+            const VT pv = __builtin_nontemporal_load((const VT*)pg + i);
+            const VT qv = __builtin_nontemporal_load((const VT*)qg + i);
+#pragma unroll
+            for (int c = 0; c < W; ++c) {
+                xv[c] = fmat(alpha, pv[c], xv[c]);
+                rv[c] = fmat(-alpha, qv[c], rv[c]);
+                s += (double)rv[c] * (double)rv[c];
+            }
+            __builtin_nontemporal_store(xv, (VT*)xg + i);
+            __builtin_nontemporal_store(rv, (VT*)rg + i);
+        }
+    }
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; !streaming && !defer && i < nv; i += stride) {
         VT xv = ((VT*)xg)[i], rv = ((VT*)rg)[i];
         const VT pv = ((const VT*)pg)[i], qv = ((const VT*)qg)[i];
 #pragma unroll
@@ -469,8 +484,11 @@ hipError_t cg_update(T* x, T* r, const T* p, const T* q, int64_t n, int nrhs, Cg
                      int part_stride, uint32_t* counters, SolveCounters* cnt, hipStream_t s, double* hist,
                      int hist_len, ResHist rh) {
     dim3 grid(vec_blocks_per_rhs(n), nrhs);
+    // the four vectors of every right-hand side at once beyond the 256 MiB last-level cache:
+    // nothing of them survives to their next use, so they bypass it (non-temporal accesses)
+    const int streaming = 4.0 * (double)n * nrhs * sizeof(T) > 256.0 * (1 << 20) ? 1 : 0;
     hipLaunchKernelGGL(k_cg_update<T>, grid, dim3(kThreads), 0, s, x, r, p, q, n, cg, partials, part_stride,
-                       counters, cnt, hist, hist_len, rh);
+                       counters, cnt, hist, hist_len, rh, streaming);
     return hipGetLastError();
 }
 template hipError_t cg_update<float>(float*, float*, const float*, const float*, int64_t, int, CgState*, double*,

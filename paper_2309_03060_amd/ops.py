@@ -289,7 +289,8 @@ class KronOperator:
         L.check("cola_autotune", self.lib.cola_autotune(self.handle, nrhs, _stream_ptr()))
 
     def set_engine(self, name: str, enable: bool):
-        """Switch one kernel engine on or off ("fused_cg", "gemm2", "gemm3", "slab", "resident", "small64")."""
+        """Switch one kernel engine on or off ("fused_cg", "gemm2", "gemm3", "slab", "resident", "small64",
+        "gemm64")."""
         if name not in L.ENGINE_BY_NAME:
             raise ValueError(f"unknown engine {name!r}; one of {sorted(L.ENGINE_BY_NAME)}")
         L.check("cola_op_set_engine",
