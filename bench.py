@@ -586,6 +586,14 @@ MFMA_PEAK_TFLOPS = {"fp32": FP32_MFMA_PEAK_TFLOPS, "bf16": 2500.0, "bf16x3": 250
 PRODUCTS_PER_FLOP = {"fp32": 1, "bf16": 1, "bf16x3": 6, "fp64": 1}
 
 
+ENGINE_NOTE = {
+    "c4": "mixed on the BF16x3 three-GEMM engine (its FP64 reliable-update residuals on the FP64 three-GEMM "
+          "engine), fp64_cg on the FP64 three-GEMM engine: both sides on dense matrix-core GEMMs",
+    "c5": "mixed on the BF16 two-GEMM engine (FP64 residuals on the FP64 two-GEMM engine), fp64_cg on the FP64 "
+          "two-GEMM engine",
+}
+
+
 def class_model(cls, prec, n, dims, J, has_diag, deferral):
     """(algorithmic FLOPs, algorithmic HBM bytes) per right-hand-side iteration of one launch class of the
     low-precision MVM and CG update (FP32 working vectors: 4 bytes a word), or None for other classes.
@@ -746,13 +754,16 @@ def run_single(args, name):
                         "rhs_iters": sum(r["iters"] for r in rec),
                         "relres_max": max(r["relres"] for r in rec), "status": sorted({r["status"] for r in rec}),
                         "rhs_iters_per_s": round(sum(r["iters"] for r in rec) / sec, 1)}
+            res[lab]["relres_recursive_max"] = max(r["relres_recursive"] for r in rec)
             if lab == "mixed":
                 res[lab]["precision"] = prec
-                res[lab]["relres_kind"] = "FP64 true residual"
+                res[lab]["stops_on"] = "FP64 true residual"
             else:
-                res[lab]["relres_kind"] = "recursive FP64 residual"
+                res[lab]["stops_on"] = "recursive FP64 residual"
             progress(f"time-to-solution {lab}: {res[lab]['seconds']} s")
         res["speedup"] = round(res["fp64_cg"]["seconds"] / res["mixed"]["seconds"], 3)
+        res["note"] = ("relres_max is the FP64 true residual of the returned x for both; "
+                       "speedup = fp64_cg seconds / mixed seconds; engines: " + ENGINE_NOTE.get(name, "general passes"))
         tts = res
     direct = None
     if name in ("c4",) and not args.no_tts:
@@ -1176,8 +1187,13 @@ def run_c2(args):
         progress("time-to-solution on the separate-kernel path done")
         res["direct_eig_solve"] = direct_solve(op, B, nrhs, n, res["mixed_fp32_reliable"]["seconds"])
         res["slq_logdet"] = slq_measure(op, s.factors[0], s.sigma2, n)
-        res["note"] = ("fp64_cg relres is its recursive residual; mixed relres is the FP64 true residual; "
-                       "speedup = fp64_cg seconds / mixed_fp32_reliable seconds")
+        res["speedup_same_kernels"] = round(res["fp64_cg"]["seconds"] /
+                                            res["mixed_fp32_reliable_separate_kernels"]["seconds"], 3)
+        res["note"] = ("relres_max is the FP64 true residual of the returned x for every solve; "
+                       "speedup = fp64_cg seconds / mixed_fp32_reliable seconds, where the mixed solve runs on "
+                       "the persistent fused FP32 engine and fp64_cg on the separate FP64 kernels (slab, "
+                       "contraction, update); speedup_same_kernels compares fp64_cg with the mixed solve on "
+                       "the same separate kernels in FP32")
         tts = res
 
     cpu = None

@@ -225,6 +225,65 @@ int32_t enqueue_mvm(cola_op_s* op, const SysInfo& s, int prec, int nrhs, const v
             return COLA_OK;
         }
     }
+    if (prec == COLA_PREC_FP64 && op->use_gemm64 && tmpl.epi != EPI_STORE && !tmpl.Ex &&
+        gemm64_3_supported(s.Fv, s.J, s.dims) &&
+        (tmpl.epi == EPI_MATVEC ||
+         gemm64_3_blocks_per_rhs(s.dims[0], s.dims[1], s.dims[2]) <= tmpl.part_stride)) {
+        // one-term three-mode operator in FP64: three dense FP64 GEMM passes, the last with the epilogue
+        const int64_t n1 = s.dims[0], n2 = s.dims[1], n3 = s.dims[2];
+        Gemm64Args g;
+        std::memset(&g, 0, sizeof(g));
+        g.J = 1;
+        g.nrhs = nrhs;
+        const bool cg = tmpl.epi == EPI_CG;
+        g.Pold = cg ? (const double*)X : nullptr;
+        g.R = cg ? (const double*)Rpnew : nullptr;
+        g.P = cg ? (double*)tmpl.Epout : nullptr;
+        g.Ep = cg ? g.P : (const double*)tmpl.Ep;
+        g.Er = (const double*)tmpl.Er;
+        g.dvec = (const double*)diag;
+        g.sigma2 = s.sigma2;
+        g.epi = tmpl.epi;
+        g.cg = tmpl.cg;
+        g.outer = tmpl.outer;
+        g.gate = tmpl.gate;
+        g.gate_stride = tmpl.gate_stride;
+        g.partials = tmpl.partials;
+        g.part_stride = tmpl.part_stride;
+        g.counters = tmpl.counters;
+        g.cnt = tmpl.cnt;
+        const double* in3 = cg ? g.P : (const double*)X;
+        auto al16 = [](const void* q) { return ((uintptr_t)q & 15) == 0; };
+        const double* f3 = op->fac64 + s.fac_off[2];
+        const double* f2 = op->fac64 + s.fac_off[1];
+        const double* f1 = op->fac64 + s.fac_off[0];
+        if (al16(in3) && al16(g.R) && al16(g.Pold) && al16(g.Ep) && al16(g.Er) && al16(g.dvec) && al16(Yout) &&
+            al16(inter[0]) && al16(inter[1]) && al16(f1) && al16(f2) && al16(f3)) {
+            if (cg) {
+                Gemm64Args gp = g;
+                gp.n1 = (int32_t)(n1 * n2);
+                gp.n2 = (int32_t)n3;
+                ProfScope ps(prof, "gemm_pack_fp64", st);
+                HIP_TRY(launch_gemm64(gp, 0, st));
+            }
+            const char* names[3] = {"gemm_mode3_fp64", "gemm_mode2_fp64", "gemm_mode1_fp64"};
+            for (int m = 3; m >= 1; --m) {
+                Gemm64Args gm = g;
+                if (m == 3) {
+                    gm.n1 = (int32_t)(n1 * n2); gm.n2 = (int32_t)n3; gm.V = f3; gm.X = in3; gm.T = (double*)inter[0];
+                } else if (m == 2) {
+                    gm.n1 = (int32_t)(n3 * n1); gm.n2 = (int32_t)n2; gm.V = f2; gm.X = (const double*)inter[0];
+                    gm.T = (double*)inter[1];
+                } else {
+                    gm.n1 = (int32_t)(n2 * n3); gm.n2 = (int32_t)n1; gm.V = f1; gm.X = (const double*)inter[1];
+                    gm.Y = (double*)Yout;
+                }
+                ProfScope ps(prof, names[3 - m], st);
+                HIP_TRY(launch_gemm64_pass(gm, m == 1, st));
+            }
+            return COLA_OK;
+        }
+    }
     if (op->use_gemm2 && (tmpl.epi == EPI_CG || tmpl.epi == EPI_MATVEC) && gemm2_supported(prec, s.Fv, s.dims)) {
         // large two-mode operator in BF16: both mode products as dense GEMMs
         Gemm2Args g;

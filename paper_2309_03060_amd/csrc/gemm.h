@@ -81,4 +81,13 @@ hipError_t launch_gemm64(const Gemm64Args& a, int stage, hipStream_t s);
 // Blocks per right-hand side of the FP64 G2.
 int64_t gemm64_blocks_per_rhs(int64_t n1, int64_t n2);
 
+// One-term three-mode operators with every mode a multiple of 256 in FP64: three passes of the
+// G1 kernel (J = 1), each contracting the contiguous mode of its input and storing its output
+// new mode first (n1 = rows per right-hand side of the pass's input, n2 = its mode size); the
+// last pass (`final`) carries the epilogue of G2 and writes Y in the original layout.  The pack
+// pass of CG is launch_gemm64 stage 0 with n1 * n2 = n.
+bool gemm64_3_supported(int Fv, int J, const int64_t* dims);
+int64_t gemm64_3_blocks_per_rhs(int64_t n1, int64_t n2, int64_t n3);
+hipError_t launch_gemm64_pass(const Gemm64Args& a, bool final, hipStream_t s);
+
 }  // namespace cola

@@ -445,10 +445,72 @@ __global__ __launch_bounds__(kThreads) void k_gemm64_pack(Gemm64Args a) {
     }
 }
 
+// The epilogue of a final pass for 4 accumulator values (elements at g + o[v] of the packed
+// vectors, d at e + o[v]): y = acc + (sigma2 + d) x, then p.q (CG) or the residual b - y and its
+// square (RESID); stores y.  Returns the updated dot-product chain.
+__device__ __attribute__((always_inline)) inline double g64_epilogue4(const Gemm64Args& a, doublex4 acc,
+                                                                     int64_t g, int64_t e, const int64_t (&o)[4],
+                                                                     double dot) {
+    const int epi = a.epi;
+    double xv[4], bv[4], dv[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        xv[v] = epi != EPI_STORE ? a.Ep[g + o[v]] : 0.0;
+        bv[v] = (epi == EPI_RESID || epi == EPI_RESID_CG) ? a.Er[g + o[v]] : 0.0;
+        dv[v] = a.dvec ? a.dvec[e + o[v]] : 0.0;
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        double y = acc[v];
+        if (epi != EPI_STORE) y = __builtin_fma(a.sigma2 + dv[v], xv[v], y);
+        if (epi == EPI_CG) {
+            dot = __builtin_fma(xv[v], y, dot);
+        } else if (epi == EPI_RESID || epi == EPI_RESID_CG) {
+            y = bv[v] - y;
+            dot = __builtin_fma(y, y, dot);
+        }
+        a.Y[g + o[v]] = y;
+    }
+    return dot;
+}
+
+// Per right-hand side reduction of the final pass's dot products and its consequence: the CG
+// step length (or a breakdown), the true residual of a reliable update, or a refinement sweep's
+// verdict.  tpr blocks per right-hand side, this block being number t of right-hand side r.
+__device__ inline void g64_finish(const Gemm64Args& a, int r, int tpr, int t, double dot, double* red) {
+    const int epi = a.epi;
+    if (epi != EPI_CG && epi != EPI_RESID && epi != EPI_RESID_CG) return;
+    const double s = block_sum8(dot, red);
+    double tot;
+    if (last_block_reduce8(s, a.partials + (int64_t)r * a.part_stride, a.counters + r, tpr, t, &tot, red) &&
+        threadIdx.x == 0) {
+        if (epi == EPI_CG) {
+            CgState& st = a.cg[r];
+            if (!(tot > 0.0) || !finite_d(tot)) {
+                st.status = finite_d(tot) ? COLA_ERR_NOT_SPD : COLA_ERR_NONFINITE;
+                st.active = 0;
+                atomicSub(&a.cnt->num_active, 1);
+            } else {
+                st.alpha = st.rho / tot;
+            }
+        } else if (epi == EPI_RESID_CG) {
+            a.cg[r].rho_true = tot;
+        } else {
+            outer_residual(a.outer[r], tot, a.cnt);
+        }
+    }
+}
+
 // G1: A = rows of [V_1; ..; V_J] (256 per tile, one term), B = rows of X (128 per tile, one
-// right-hand side); the accumulator tile is T_r[b][(j, a')] with a' along the lanes.
+// right-hand side); the accumulator tile is T_r[b][(j, a')] with a' along the lanes.  The
+// mode passes of a one-term three-mode operator are this kernel with J = 1, n1 = the rows per
+// right-hand side and n2 = the contracted (and output) mode: T is then Out[r][b][a'], the output
+// stored new mode first.  FINAL (three-mode, J = 1): the last pass, whose Out is the product in
+// its own layout, with the epilogue of the final pass instead of a plain store.
+template <bool FINAL>
 __global__ __launch_bounds__(kGT) void k_gemm64_t(Gemm64Args a) {
     __shared__ __attribute__((aligned(16))) char smem[2 * kDStage];
+    __shared__ double red[8];
     const int Mt = a.J * a.n2 / DM, Nt = a.nrhs * a.n1 / DN;
     const int L = xcd_linear(blockIdx.x, Mt * Nt);
     const int mt = L % Mt, nt = L / Mt;                    // the A panels of all terms cycle fastest
@@ -469,13 +531,31 @@ __global__ __launch_bounds__(kGT) void k_gemm64_t(Gemm64Args a) {
     const int jt = (int)(m0 / n2);
     const int64_t b_lane = m0 - (int64_t)jt * n2 + wa * 64 + (lane >> 4);
     const int64_t a_lane = n0 - (int64_t)r * a.n1 + wb * 64 + (lane & 15);
-    double* const out = a.T + ((int64_t)r * n2 + b_lane) * ldt + (int64_t)jt * a.n1 + a_lane;
+    if constexpr (!FINAL) {
+        double* const out = a.T + ((int64_t)r * n2 + b_lane) * ldt + (int64_t)jt * a.n1 + a_lane;
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+            for (int j = 0; j < 4; ++j)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) out[(int64_t)(16 * i + 4 * v) * ldt + 16 * j] = acc[i][j][v];
+                for (int v = 0; v < 4; ++v) out[(int64_t)(16 * i + 4 * v) * ldt + 16 * j] = acc[i][j][v];
+    } else {
+        const int64_t n = n2 * a.n1;                       // elements per right-hand side
+        const int64_t e_lane = b_lane * a.n1 + a_lane;
+        const int64_t g_lane = (int64_t)r * n + e_lane;
+        double dot = 0.0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                int64_t o[4];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) o[v] = (int64_t)(16 * i + 4 * v) * a.n1 + 16 * j;
+                dot = g64_epilogue4(a, acc[i][j], g_lane, e_lane, o, dot);
+            }
+        const int bpr = a.n1 / DN;                         // B tiles per right-hand side
+        g64_finish(a, r, Mt * bpr, mt + Mt * (nt - r * bpr), dot, red);
+    }
 }
 
 // G2: A = rows a of [U_1 .. U_J] (k = (j, a')), B = rows b of T_r; the accumulator tile is
@@ -506,55 +586,17 @@ __global__ __launch_bounds__(kGT) void k_gemm64_y(Gemm64Args a) {
     const int64_t n = n1 * n2;
     const int64_t e_lane = (int64_t)(a0 + wa * 64 + (lane >> 4)) * n2 + b0 + wb * 64 + (lane & 15);
     const int64_t g_lane = (int64_t)r * n + e_lane;
-    const int epi = a.epi;
-    const double s2 = a.sigma2;
     double dot = 0.0;
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            double xv[4], bv[4], dv[4];
+            int64_t o[4];
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int64_t o = (int64_t)(16 * i + 4 * v) * n2 + 16 * j;
-                xv[v] = epi != EPI_STORE ? a.Ep[g_lane + o] : 0.0;
-                bv[v] = (epi == EPI_RESID || epi == EPI_RESID_CG) ? a.Er[g_lane + o] : 0.0;
-                dv[v] = a.dvec ? a.dvec[e_lane + o] : 0.0;
-            }
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int64_t o = (int64_t)(16 * i + 4 * v) * n2 + 16 * j;
-                double y = acc[i][j][v];
-                if (epi != EPI_STORE) y = __builtin_fma(s2 + dv[v], xv[v], y);
-                if (epi == EPI_CG) {
-                    dot = __builtin_fma(xv[v], y, dot);
-                } else if (epi == EPI_RESID || epi == EPI_RESID_CG) {
-                    y = bv[v] - y;
-                    dot = __builtin_fma(y, y, dot);
-                }
-                a.Y[g_lane + o] = y;
-            }
+            for (int v = 0; v < 4; ++v) o[v] = (int64_t)(16 * i + 4 * v) * n2 + 16 * j;
+            dot = g64_epilogue4(a, acc[i][j], g_lane, e_lane, o, dot);
         }
-    if (epi != EPI_CG && epi != EPI_RESID && epi != EPI_RESID_CG) return;
-    const double s = block_sum8(dot, red);
-    double tot;
-    if (last_block_reduce8(s, a.partials + (int64_t)r * a.part_stride, a.counters + r, tpr, t, &tot, red) &&
-        threadIdx.x == 0) {
-        if (epi == EPI_CG) {
-            CgState& st = a.cg[r];
-            if (!(tot > 0.0) || !finite_d(tot)) {
-                st.status = finite_d(tot) ? COLA_ERR_NOT_SPD : COLA_ERR_NONFINITE;
-                st.active = 0;
-                atomicSub(&a.cnt->num_active, 1);
-            } else {
-                st.alpha = st.rho / tot;
-            }
-        } else if (epi == EPI_RESID_CG) {
-            a.cg[r].rho_true = tot;
-        } else {
-            outer_residual(a.outer[r], tot, a.cnt);
-        }
-    }
+    g64_finish(a, r, tpr, t, dot, red);
 }
 
 }  // namespace
@@ -572,6 +614,31 @@ bool gemm64_supported(int Fv, const int64_t* dims) {
 
 int64_t gemm64_blocks_per_rhs(int64_t n1, int64_t n2) { return (n1 / DM) * (n2 / DN); }
 
+bool gemm64_3_supported(int Fv, int J, const int64_t* dims) {
+    return Fv == 3 && J == 1 && dims[0] >= DM && dims[1] >= DM && dims[2] >= DM && dims[0] % DM == 0 &&
+           dims[1] % DM == 0 && dims[2] % DM == 0;
+}
+
+int64_t gemm64_3_blocks_per_rhs(int64_t n1, int64_t n2, int64_t n3) { return (n1 / DM) * (n2 * n3 / DN); }
+
+hipError_t launch_gemm64_pass(const Gemm64Args& a, bool final, hipStream_t s) {
+    if (a.n2 % DM || a.n1 % DN || a.n1 < DN || a.n2 < DM || a.nrhs < 1 || a.J != 1 || !a.X || !a.V)
+        return hipErrorInvalidValue;
+    if (final) {
+        const bool cg = a.epi == EPI_CG;
+        const bool resid = a.epi == EPI_RESID || a.epi == EPI_RESID_CG;
+        if ((cg && !a.cg) || (resid && !a.Er) || (a.epi == EPI_RESID && !a.outer) ||
+            (a.epi == EPI_RESID_CG && !a.cg) || (a.epi != EPI_STORE && !a.Ep) || !a.Y)
+            return hipErrorInvalidValue;
+    } else if (!a.T) {
+        return hipErrorInvalidValue;
+    }
+    const int64_t T = (int64_t)(a.n2 / DM) * (a.nrhs * (int64_t)a.n1 / DN);
+    if (final) hipLaunchKernelGGL(k_gemm64_t<true>, dim3((unsigned)T), dim3(kGT), 0, s, a);
+    else hipLaunchKernelGGL(k_gemm64_t<false>, dim3((unsigned)T), dim3(kGT), 0, s, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_gemm64(const Gemm64Args& a, int stage, hipStream_t s) {
     const int64_t dims[2] = {a.n1, a.n2};
     if (!gemm64_supported(2, dims) || a.nrhs < 1 || a.J < 1) return hipErrorInvalidValue;
@@ -587,7 +654,7 @@ hipError_t launch_gemm64(const Gemm64Args& a, int stage, hipStream_t s) {
         hipLaunchKernelGGL(k_gemm64_pack, dim3((unsigned)bx, (unsigned)a.nrhs), dim3(kThreads), 0, s, a);
     } else if (stage == 1) {
         const int64_t T = (int64_t)(a.J * a.n2 / DM) * (a.nrhs * (int64_t)a.n1 / DN);
-        hipLaunchKernelGGL(k_gemm64_t, dim3((unsigned)T), dim3(kGT), 0, s, a);
+        hipLaunchKernelGGL(k_gemm64_t<false>, dim3((unsigned)T), dim3(kGT), 0, s, a);
     } else {
         const int64_t T = (int64_t)a.nrhs * gemm64_blocks_per_rhs(a.n1, a.n2);
         hipLaunchKernelGGL(k_gemm64_y, dim3((unsigned)T), dim3(kGT), 0, s, a);

@@ -113,3 +113,68 @@ def test_mixed_solve_residuals_on_engine(refine):
     for i, r in zip(rec, rr):
         assert i["status"] == 0 and r <= 1e-10, (rec, rr)
         assert abs(i["relres_true"] - r) <= 1e-3 * r, (i, r)
+
+
+# One-term three-mode operators with every mode a multiple of 256: three FP64 GEMM passes, the
+# last with the epilogue (the FP64 side of the 256^3 workload: plain FP64 CG and the residuals of
+# its mixed-precision solves).
+@pytest.mark.parametrize("dims,diag,nrhs", [((256, 256, 256), True, 2), ((512, 256, 256), False, 1)])
+def test_fp64_three_mode_product_against_oracle(dims, diag, nrhs):
+    import torch
+    from gpu_util import make_op, pack, unpack
+    rng = np.random.default_rng(sum(dims) + nrhs)
+    s = wl.random_system(rng, dims, nterms=1, diag=diag, sigma2=0.3)
+    X = rng.standard_normal((nrhs, s.n))
+    op = make_op([s], prec="fp32")
+    op.profile_enable(True)
+    Y = unpack(op.matvec(pack([X]), nrhs, prec="fp64"), [s], nrhs)[0]
+    torch.cuda.synchronize()
+    _, launches = op.profile_read("gemm_mode3_fp64")
+    op.profile_enable(False)
+    assert launches == 1
+    op.set_engine("gemm64", False)
+    Yg = unpack(op.matvec(pack([X]), nrhs, prec="fp64"), [s], nrhs)[0]
+    op.close()
+    ref = kron.mvm(s.factors, X, s.sigma2, s.diag)
+    bound = _fp64_bound(s, X)
+    k = sum(dims) + 2
+    assert np.all(np.abs(Y - ref) <= k * 2.0 ** -53 * bound), np.max(np.abs(Y - ref) / bound)
+    assert np.all(np.abs(Y - Yg) <= k * 2.0 ** -52 * bound)
+
+
+def test_fp64_three_mode_cg_and_mixed_residuals():
+    """256^3 Wishart operator: plain FP64 CG on the engine (pack + three passes with the CG epilogue)
+    against the general passes (iteration counts within one, both certified by the oracle's
+    residual), and a BF16x3 solve whose FP64 reliable-update residuals run on the engine, certified
+    to 1e-9 with its reported true residual equal to the oracle's."""
+    import torch
+    from gpu_util import infos, make_op, pack, unpack
+    rng = np.random.default_rng(256)
+    s = wl.random_system(rng, (256, 256, 256), nterms=1, diag=False, sigma2=0.1)
+    nrhs = 2
+    B = rng.standard_normal((nrhs, s.n))
+    op = make_op([s], prec="bf16x3")
+    op.profile_enable(True)
+    X, info = op.solve(pack([B]), nrhs, prec="fp64", tol=1e-10, max_iters=500)
+    torch.cuda.synchronize()
+    _, launches = op.profile_read("gemm_pack_fp64")
+    op.profile_enable(False)
+    rec = infos(info, nrhs)
+    Xh = unpack(X, [s], nrhs)[0]
+    Xm, infom = op.solve(pack([B]), nrhs, prec="bf16x3", tol=1e-9, max_iters=2000, inner_tol=0.1)
+    recm = infos(infom, nrhs)
+    Xmh = unpack(Xm, [s], nrhs)[0]
+    op.set_engine("gemm64", False)
+    X2, info2 = op.solve(pack([B]), nrhs, prec="fp64", tol=1e-10, max_iters=500)
+    rec2 = infos(info2, nrhs)
+    op.close()
+    assert launches >= 5
+    rr = kron.relres(s.factors, Xh, B, s.sigma2)
+    rr2 = kron.relres(s.factors, unpack(X2, [s], nrhs)[0], B, s.sigma2)
+    rrm = kron.relres(s.factors, Xmh, B, s.sigma2)
+    for r in range(nrhs):
+        assert rec[r]["status"] == 0 and rec2[r]["status"] == 0 and recm[r]["status"] == 0
+        assert abs(rec[r]["iters"] - rec2[r]["iters"]) <= 1, (rec, rec2)
+        assert rr[r] <= 2e-10 and rr2[r] <= 2e-10, (rr, rr2)
+        assert abs(rec[r]["relres_true"] - rr[r]) <= 1e-3 * rr[r]
+        assert rrm[r] <= 1e-9 and abs(recm[r]["relres_true"] - rrm[r]) <= 1e-3 * rrm[r], (recm, rrm)
