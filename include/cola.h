@@ -359,6 +359,12 @@ int32_t cola_profile_enable(cola_op_t op, int32_t enable);
  * synchronises the device.  Unknown names report zero launches. */
 int32_t cola_profile_read(cola_op_t op, const char* kernel, double* total_ms, int64_t* launches);
 
+/* Host-side ranges of every entry point (and of each system's solve, reliable update and
+ * final fold) as roctx ranges, for rocprofv3 --marker-trace: on for enable != 0, process-wide,
+ * off by default (a disabled range costs one atomic load).  For the callers that profile.
+ * Always returns COLA_OK. */
+int32_t cola_trace_enable(int32_t enable);
+
 /* Static description of a status code. */
 const char* cola_status_string(int32_t status);
 

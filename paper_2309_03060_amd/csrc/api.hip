@@ -9,9 +9,12 @@
 #include <cstdio>
 #include <cstring>
 #include <mutex>
+
+#include <rocprofiler-sdk-roctx/roctx.h>
 #include <new>
 
 #include "gemm.h"
+#include "trace.h"
 #include "eig.h"
 #include "fused.h"
 #include "gemm3.h"
@@ -527,6 +530,7 @@ struct ReliableTail {
 // x has not changed since.
 int32_t enqueue_tail(cola_op_s* op, const SysInfo& s, int nrhs, const ReliableTail& t, bool final,
                      hipStream_t st) {
+    TraceRange trace_range(final ? "reliable_final" : "reliable_update");
     Workspace& w = op->ws;
     if (final) HIP_TRY(mark_unverified(w.cg, nrhs, st));
     HIP_TRY(reliable_fold<float>(t.X, t.xl, t.pl, s.n, nrhs, w.cg, false, st));
@@ -980,6 +984,7 @@ int32_t run_pcg(cola_op_s* op, const SysInfo& s, const double* B, double* X, int
 
 int32_t solve_system(cola_op_s* op, const SysInfo& s, const double* B, double* X, int nrhs,
                      const cola_solve_opts* o, cola_solve_info* info, hipStream_t st) {
+    TraceRange trace_range("solve_system");
     Workspace& w = op->ws;
     const int64_t n = s.n;
     const int ps = (int)w.part_stride;
@@ -1314,6 +1319,7 @@ const char* cola_status_string(int32_t status) {
 
 int32_t cola_op_create(const cola_system_desc* systems, int32_t nsys, int32_t prec, void* stream,
                        cola_op_t* out) {
+    TraceRange trace_range("cola_op_create");
     if (!out) return COLA_ERR_INVALID_ARG;
     *out = nullptr;
     if (!systems || nsys < 1) return COLA_ERR_INVALID_ARG;
@@ -1523,6 +1529,7 @@ int32_t ensure_eig(cola_op_s* op, hipStream_t st) {
 }  // namespace
 
 int32_t cola_op_diagonal(cola_op_t op, double* out, void* stream) {
+    TraceRange trace_range("cola_op_diagonal");
     if (!op || !out) return COLA_ERR_INVALID_ARG;
     hipStream_t st = S(stream);
     for (const SysInfo& s : op->sys) HIP_TRY(kron_diagonal(diag_args(op, s), out + s.vec_off, false, st));
@@ -1531,6 +1538,7 @@ int32_t cola_op_diagonal(cola_op_t op, double* out, void* stream) {
 
 int32_t cola_diag_estimate(cola_op_t op, const double* Z, int32_t nprobes, int32_t mode, double* out,
                            void* stream) {
+    TraceRange trace_range("cola_diag_estimate");
     if (!op || !Z || !out || nprobes < 1) return COLA_ERR_INVALID_ARG;
     if (mode != COLA_DIAG_HUTCHINSON && mode != COLA_DIAG_DOUBLY) return COLA_ERR_INVALID_ARG;
     hipStream_t st = S(stream);
@@ -1575,6 +1583,7 @@ int32_t cola_diag_estimate(cola_op_t op, const double* Z, int32_t nprobes, int32
 }
 
 int32_t cola_eig_solve(cola_op_t op, const double* B, double* X, int32_t nrhs, void* stream) {
+    TraceRange trace_range("cola_eig_solve");
     if (!op || !B || !X || nrhs < 1) return COLA_ERR_INVALID_ARG;
     for (const SysInfo& s : op->sys)
         if (s.J != 1 || s.diag_off >= 0) return COLA_ERR_UNSUPPORTED;
@@ -1639,6 +1648,7 @@ int32_t cola_op_size(cola_op_t op, int64_t* n_total, int32_t* nsys) {
 
 int32_t cola_kron_matvec(cola_op_t op, const void* X, void* Y, int32_t nrhs, int32_t dtype, int32_t prec,
                          void* stream) {
+    TraceRange trace_range("cola_kron_matvec");
     if (!op || !X || !Y || nrhs < 1) return COLA_ERR_INVALID_ARG;
     if (prec == COLA_PREC_FP64) {
         if (dtype != COLA_F64) return COLA_ERR_INVALID_ARG;
@@ -1663,6 +1673,7 @@ int32_t cola_kron_matvec(cola_op_t op, const void* X, void* Y, int32_t nrhs, int
 
 int32_t cola_kron_matvec_noalloc(cola_op_t op, const void* X, void* Y, int32_t nrhs, int32_t dtype, int32_t prec,
                                  void* stream) {
+    TraceRange trace_range("cola_kron_matvec_noalloc");
     if (!op || !X || !Y || nrhs < 1) return COLA_ERR_INVALID_ARG;
     if (prec == COLA_PREC_FP64) {
         if (dtype != COLA_F64) return COLA_ERR_INVALID_ARG;
@@ -1696,6 +1707,7 @@ int32_t cola_kron_matvec_noalloc(cola_op_t op, const void* X, void* Y, int32_t n
 
 int32_t cola_cg_solve(cola_op_t op, const double* B, double* X, int32_t nrhs, const cola_solve_opts* opts,
                       cola_solve_info* info, void* stream) {
+    TraceRange trace_range("cola_cg_solve");
     if (!op || !B || !X || nrhs < 1) return COLA_ERR_INVALID_ARG;
     int32_t rc = check_opts(op, opts);
     if (rc != COLA_OK) return rc;
@@ -1730,6 +1742,7 @@ int32_t cola_cg_solve(cola_op_t op, const double* B, double* X, int32_t nrhs, co
 
 int32_t cola_slq_logdet(cola_op_t op, const double* Z, int32_t nprobes, double tol, int32_t max_iters,
                         double* X, double* logdet, double* est, cola_solve_info* info, void* stream) {
+    TraceRange trace_range("cola_slq_logdet");
     if (!op || !Z || !logdet || nprobes < 1 || !finite_pos(tol) || max_iters < 1) return COLA_ERR_INVALID_ARG;
     if (max_iters > kSlqMaxSteps) return COLA_ERR_INVALID_ARG;
     hipStream_t st = S(stream);
@@ -1769,6 +1782,7 @@ int32_t cola_slq_logdet(cola_op_t op, const double* Z, int32_t nprobes, double t
 int32_t cola_cg_solve_backward(cola_op_t op, const double* X, const double* G, int32_t nrhs,
                                const cola_solve_opts* opts, double* Lambda, void* const* dfactors,
                                void* const* ddiag, double* dsigma2, cola_solve_info* info, void* stream) {
+    TraceRange trace_range("cola_cg_solve_backward");
     if (!op || !X || !G || !Lambda || nrhs < 1) return COLA_ERR_INVALID_ARG;
     int32_t rc = cola_cg_solve(op, G, Lambda, nrhs, opts, info, stream);
     if (rc != COLA_OK) return rc;
@@ -1790,6 +1804,7 @@ int32_t cola_cg_solve_backward(cola_op_t op, const double* X, const double* G, i
 int32_t cola_logdet_grad(cola_op_t op, const double* Z, int32_t nprobes, const cola_solve_opts* opts,
                          double* Lambda, void* const* dfactors, void* const* ddiag, double* dsigma2,
                          cola_solve_info* info, void* stream) {
+    TraceRange trace_range("cola_logdet_grad");
     if (!op || !Z || !Lambda || nprobes < 1) return COLA_ERR_INVALID_ARG;
     int32_t rc = cola_cg_solve(op, Z, Lambda, nprobes, opts, info, stream);      // Lambda = A^{-1} Z
     if (rc != COLA_OK) return rc;
@@ -1804,6 +1819,11 @@ int32_t cola_logdet_grad(cola_op_t op, const double* Z, int32_t nprobes, const c
                          ddiag ? ddiag[i] : nullptr, dsigma2 ? dsigma2 + i : nullptr, st, scale);
         if (rc != COLA_OK) return rc;
     }
+    return COLA_OK;
+}
+
+int32_t cola_trace_enable(int32_t enable) {
+    g_trace_on.store(enable != 0 ? 1 : 0, std::memory_order_relaxed);
     return COLA_OK;
 }
 
@@ -1826,6 +1846,7 @@ int32_t cola_op_set_engine(cola_op_t op, int32_t engine, int32_t enable) {
 }
 
 int32_t cola_autotune(cola_op_t op, int32_t nrhs, void* stream) {
+    TraceRange trace_range("cola_autotune");
     if (!op || nrhs < 1) return COLA_ERR_INVALID_ARG;
     return autotune_op(op, nrhs, S(stream));
 }
@@ -1849,6 +1870,16 @@ int32_t cola_profile_read(cola_op_t op, const char* kernel, double* total_ms, in
 
 // ===========================================================================
 namespace cola {
+
+std::atomic<int> g_trace_on{0};
+
+TraceRange::TraceRange(const char* name) : on(g_trace_on.load(std::memory_order_relaxed) != 0) {
+    if (on) roctxRangePushA(name);
+}
+
+TraceRange::~TraceRange() {
+    if (on) roctxRangePop();
+}
 
 int32_t ensure_workspace(cola_op_s* op, int nrhs, hipStream_t st) { return ensure_ws(op, nrhs, st); }
 

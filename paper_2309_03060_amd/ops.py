@@ -303,6 +303,12 @@ class KronOperator:
                                                           1 if reset_peak else 0))
         return live.value, peak.value
 
+    @staticmethod
+    def trace_enable(on: bool = True):
+        """Process-wide roctx ranges around the library's calls (cola_trace_enable), for
+        rocprofv3 --marker-trace."""
+        L.check("cola_trace_enable", L.lib().cola_trace_enable(1 if on else 0))
+
     def profile_enable(self, on: bool = True):
         L.check("cola_profile_enable", self.lib.cola_profile_enable(self.handle, 1 if on else 0))
 
