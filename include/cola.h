@@ -319,6 +319,20 @@ int32_t cola_eig_solve(cola_op_t op, const double* B, double* X, int32_t nrhs, v
  * `stream` (synchronises it).  Optional: without it a fixed default is used. */
 int32_t cola_autotune(cola_op_t op, int32_t nrhs, void* stream);
 
+/* The op's tuned tile table as text, to keep a tuning cache across processes and ops of the same
+ * shapes: a line "device <arch> <compute units>", then one line per tuned pass,
+ * "<prec> <rows> <mode size> <inner extent> <leading extent> <wm> <wn>".  buf NULL: *len
+ * receives the length (without the terminating NUL) and nothing is written; otherwise buf (cap
+ * bytes) receives the NUL-terminated text, COLA_ERR_INVALID_ARG if it does not fit.  For callers
+ * that cache tuning results. */
+int32_t cola_autotune_export(cola_op_t op, char* buf, int64_t cap, int64_t* len);
+
+/* Load a table written by cola_autotune_export (by this or another op): entries recorded on the
+ * same device architecture and compute-unit count replace the op's own (synchronises the device
+ * and drops captured chunk graphs); entries of another device are read and ignored.
+ * COLA_ERR_INVALID_ARG for a malformed line or an invalid tile; nothing is applied then. */
+int32_t cola_autotune_import(cola_op_t op, const char* text);
+
 /* Engine switches.  Every engine is on by default and is used wherever its
  * shape conditions hold; switched off, the op uses the general per-mode
  * contraction path for those shapes instead (the same arithmetic up to

@@ -45,7 +45,7 @@ EXPORTED = ("cola_op_create", "cola_op_destroy", "cola_op_memory", "cola_op_size
             "cola_kron_matvec_noalloc",
             "cola_op_diagonal", "cola_diag_estimate",
             "cola_cg_solve", "cola_cg_solve_backward", "cola_logdet_grad", "cola_eig_solve", "cola_slq_logdet",
-            "cola_autotune",
+            "cola_autotune", "cola_autotune_export", "cola_autotune_import",
             "cola_op_set_engine", "cola_profile_enable", "cola_profile_read", "cola_trace_enable",
             "cola_status_string")
 
@@ -110,6 +110,8 @@ def lib():
         L.cola_op_set_engine.argtypes = [vp, i32, i32]
         L.cola_profile_enable.argtypes = [vp, i32]
         L.cola_trace_enable.argtypes = [i32]
+        L.cola_autotune_export.argtypes = [vp, ctypes.c_char_p, i64, ctypes.POINTER(i64)]
+        L.cola_autotune_import.argtypes = [vp, ctypes.c_char_p]
         L.cola_profile_read.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(dbl), ctypes.POINTER(i64)]
         L.cola_status_string.argtypes = [i32]
         L.cola_status_string.restype = ctypes.c_char_p

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <mutex>
+#include <string>
 
 #include <rocprofiler-sdk-roctx/roctx.h>
 #include <new>
@@ -1849,6 +1850,69 @@ int32_t cola_autotune(cola_op_t op, int32_t nrhs, void* stream) {
     TraceRange trace_range("cola_autotune");
     if (!op || nrhs < 1) return COLA_ERR_INVALID_ARG;
     return autotune_op(op, nrhs, S(stream));
+}
+
+// The device line of an exported tile table: architecture name and compute-unit count.
+static std::string tile_device_tag() {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown 0";
+    std::string arch = prop.gcnArchName;
+    const size_t colon = arch.find(':');
+    if (colon != std::string::npos) arch.resize(colon);
+    return arch + " " + std::to_string(prop.multiProcessorCount);
+}
+
+int32_t cola_autotune_export(cola_op_t op, char* buf, int64_t cap, int64_t* len) {
+    if (!op || !len || (buf && cap < 1)) return COLA_ERR_INVALID_ARG;
+    std::string s = "device " + tile_device_tag() + "\n";
+    for (const auto& kv : op->tiles) {
+        const PassKey& k = kv.first;
+        s += std::to_string(k.prec) + " " + std::to_string(k.rows) + " " + std::to_string(k.nk) + " " +
+             std::to_string(k.B) + " " + std::to_string(k.g) + " " + std::to_string(kv.second.wm) + " " +
+             std::to_string(kv.second.wn) + "\n";
+    }
+    *len = (int64_t)s.size();
+    if (!buf) return COLA_OK;
+    if ((int64_t)s.size() + 1 > cap) return COLA_ERR_INVALID_ARG;
+    std::memcpy(buf, s.c_str(), s.size() + 1);
+    return COLA_OK;
+}
+
+int32_t cola_autotune_import(cola_op_t op, const char* text) {
+    if (!op || !text) return COLA_ERR_INVALID_ARG;
+    const std::string here = tile_device_tag();
+    std::map<PassKey, TileCfg> got;
+    bool for_here = false;
+    const char* p = text;
+    while (*p) {
+        const char* e = std::strchr(p, '\n');
+        const std::string line(p, e ? (size_t)(e - p) : std::strlen(p));
+        p = e ? e + 1 : p + line.size();
+        if (line.empty()) continue;
+        if (line.compare(0, 7, "device ") == 0) {
+            for_here = line.substr(7) == here;
+            continue;
+        }
+        long long v[7];
+        int used = 0;
+        if (std::sscanf(line.c_str(), "%lld %lld %lld %lld %lld %lld %lld%n", &v[0], &v[1], &v[2], &v[3], &v[4],
+                        &v[5], &v[6], &used) != 7 || line.find_first_not_of(" \t\r", (size_t)used) != std::string::npos)
+            return COLA_ERR_INVALID_ARG;
+        const bool cfg_ok = (v[5] == 1 || v[5] == 2 || v[5] == 4) && (v[6] == 1 || v[6] == 2 || v[6] == 4);
+        const bool key_ok = v[0] >= COLA_PREC_FP64 && v[0] <= COLA_PREC_BF16X3 && (v[1] == 0 || v[1] == 1) &&
+                            v[2] >= 1 && v[3] >= 1 && v[4] >= 1;
+        if (!cfg_ok || !key_ok) return COLA_ERR_INVALID_ARG;
+        if (!for_here) continue;                         // tuned on another device: not used here
+        got[PassKey{(int)v[0], (int)v[1], (int64_t)v[2], (int64_t)v[3], (int64_t)v[4]}] =
+            TileCfg{(int)v[5], (int)v[6]};
+    }
+    if (got.empty()) return COLA_OK;
+    (void)hipDeviceSynchronize();
+    for (const auto& kv : got) op->tiles[kv.first] = kv.second;
+    destroy_graphs(op);                                  // captured chunks embed the previous tiles
+    op->tiles_version += 1;
+    return COLA_OK;
 }
 
 int32_t cola_profile_enable(cola_op_t op, int32_t enable) {

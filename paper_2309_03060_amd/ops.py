@@ -9,6 +9,8 @@ offset r * n_s), systems one after another.
 from __future__ import annotations
 
 import ctypes
+import json
+import os
 from dataclasses import dataclass
 from typing import List, Optional, Sequence
 
@@ -285,8 +287,42 @@ class KronOperator:
             info.data_ptr(), _stream_ptr()))
         return dfac, ddiag, ds2, info
 
-    def autotune(self, nrhs: int):
+    def autotune(self, nrhs: int, cache: Optional[str] = None) -> bool:
+        """Tune the tile shapes of the general contraction passes for nrhs right-hand sides.
+
+        cache: a JSON file mapping a shape signature (working precision, nrhs, every system's
+        modes and term count) to the table cola_autotune_export writes.  A hit loads the table
+        (cola_autotune_import applies only the entries recorded on this device) instead of timing
+        the candidates; a miss tunes and adds the table.  Returns True on a hit."""
+        sig = None
+        if cache is not None:
+            sig = json.dumps({"prec": int(self.prec), "nrhs": int(nrhs),
+                              "systems": [[list(map(int, s.dims)), len(s.factors), s.diag is not None]
+                                          for s in self.systems]}, sort_keys=True)
+            table = {}
+            if os.path.exists(cache):
+                with open(cache) as fh:
+                    table = json.load(fh)
+            if sig in table:
+                L.check("cola_autotune_import", self.lib.cola_autotune_import(self.handle, table[sig].encode()))
+                return True
         L.check("cola_autotune", self.lib.cola_autotune(self.handle, nrhs, _stream_ptr()))
+        if cache is not None:
+            n = ctypes.c_int64()
+            L.check("cola_autotune_export", self.lib.cola_autotune_export(self.handle, None, 0, ctypes.byref(n)))
+            buf = ctypes.create_string_buffer(int(n.value) + 1)
+            L.check("cola_autotune_export", self.lib.cola_autotune_export(self.handle, buf, n.value + 1,
+                                                                          ctypes.byref(n)))
+            table = {}
+            if os.path.exists(cache):
+                with open(cache) as fh:
+                    table = json.load(fh)
+            table[sig] = buf.value.decode()
+            tmp = cache + ".tmp"
+            with open(tmp, "w") as fh:
+                json.dump(table, fh, indent=1, sort_keys=True)
+            os.replace(tmp, cache)
+        return False
 
     def set_engine(self, name: str, enable: bool):
         """Switch one kernel engine on or off ("fused_cg", "gemm2", "gemm3", "slab", "resident", "small64",

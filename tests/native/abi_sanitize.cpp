@@ -257,6 +257,15 @@ int main() {
 
     // ---- tuning, engines, profiling ----
     ok(cola_autotune(op, nrhs, nullptr), "autotune");
+    {
+        int64_t len = 0;
+        ok(cola_autotune_export(op, nullptr, 0, &len), "tile table length");
+        std::vector<char> text((size_t)len + 1);
+        ok(cola_autotune_export(op, text.data(), len + 1, &len), "tile table export");
+        ok(cola_autotune_import(op, text.data()), "tile table import");
+        check(cola_autotune_export(op, text.data(), 1, &len) == COLA_ERR_INVALID_ARG, "export into a short buffer");
+        check(cola_autotune_import(op, "device x 1\n1 2 3\n") == COLA_ERR_INVALID_ARG, "malformed table");
+    }
     ok(cola_profile_enable(op, 1), "profile on");
     ok(cola_kron_matvec(op, dxf, dyf, nrhs, COLA_F32, COLA_PREC_FP32, nullptr), "profiled product");
     double ms = 0.0;
