@@ -31,16 +31,16 @@ def _rel(a, b):
 @pytest.mark.parametrize("prec", ["bf16x3", "fp32"])
 def test_c4_solve_certified_at_1e6(prec):
     """256^3 RBF operator (l = 0.15, sigma2 = 0.05), 8 RHS, mixed precision with FP64 reliable
-    updates to 1e-6 exactly as the benchmark runs it (inner_tol 0.1, 32 iterations per host check):
-    tens of thousands of iterations and many reliable updates on an operator of condition number
-    ~1.4e7."""
+    updates to 1e-6 exactly as the benchmark runs it (a residual replacement whenever the recursive
+    residual has fallen to 0.3 of the last true one, 32 iterations per host check): tens of
+    thousands of iterations and many reliable updates on an operator of condition number ~1.4e7."""
     from gpu_util import infos, make_op, pack, unpack
     w = wl.config4()
     s = w.systems[0]
     nrhs = 8
     op = make_op([s], prec=prec)
     op.autotune(nrhs)
-    X, info = op.solve(pack(w.B), nrhs, tol=1e-6, max_iters=60000, prec=prec, inner_tol=0.1, check_every=32)
+    X, info = op.solve(pack(w.B), nrhs, tol=1e-6, max_iters=60000, prec=prec, inner_tol=0.3, check_every=32)
     Xh = unpack(X, [s], nrhs)[0]
     rec = infos(info, nrhs)
     op.close()
