@@ -31,9 +31,12 @@ with X = x.reshape(n1, n2), matching numpy.kron and the row-major form of the
 Kronecker-diagonal rule of App. A.  Right-hand sides are rows: B has shape
 (nrhs, n).
 
-Parity status of each function is stated in its docstring; all functions
-here are pinned by tests in tests/test_oracle_*.py except the mixed
-precision refinement schedule (parity unpinned: the paper gives no
-low-precision CG steps, only a citation).
+Parity status of each function is stated in its docstring; every function
+here is pinned by tests in tests/test_oracle_*.py.  The two mixed-precision
+schedules (restarted refinement, reliable updates) are readings: the paper
+gives no low-precision CG steps, so their pins are what mathematics fixes
+(textbook CG when nothing is rounded, float64 accuracy from float32 vectors,
+a bound on the number of residual replacements, stagnation under an
+inconsistent inner operator), not printed values.
 """
 from . import kron, direct, cg, grad, lowprec  # noqa: F401

@@ -136,8 +136,9 @@ def refine(apply_A64: Callable, apply_A_low: Callable, B: np.ndarray, tol: float
     ||r|| / ||b|| <= tol; otherwise solve A_low d = r / ||r|| with CG in
     the working precision to inner_tol and update x += ||r|| d in float64.
     A sweep that fails to halve ||r|| twice in a row ends the solve as
-    "stagnated".  (parity of this schedule against the paper: unpinned;
-    only its end point, the residual, is checked.)
+    "stagnated".  (The paper fixes no schedule.  This one is pinned by what
+    mathematics fixes: float32 inner solves reach float64 accuracy, and an
+    inconsistent inner operator makes it stagnate.)
     """
     B = np.asarray(B, dtype=np.float64)
     nrhs = B.shape[0]
@@ -187,3 +188,132 @@ def refine(apply_A64: Callable, apply_A_low: Callable, B: np.ndarray, tol: float
         if active[i] and status[i] == OK and rel[i] > tol:
             status[i] = NOT_CONVERGED
     return RefineResult(X, sweeps, inner, status, rel, hist)
+
+
+@dataclass
+class ReliableResult:
+    X: np.ndarray
+    iters: np.ndarray
+    updates: np.ndarray
+    status: List[str]
+    relres_true: np.ndarray
+    relres_recursive: np.ndarray
+
+
+def reliable(apply_A64: Callable, apply_A_low: Callable, B: np.ndarray, tol: float, delta: float,
+             max_iters: int, check_every: int, low_dtype=np.float32, restart_dir: bool = False) -> ReliableResult:
+    """One low-precision CG whose residual is replaced by the float64 true residual ("reliable
+    updates"), the reading of the paper's low precision by algorithmic modification (Sec. 3.4,
+    App. C.3) that the library builds; the paper prints no scheme, so this follows that reading:
+
+    * the working vectors x_lo, r, p and the products q = A_low p are rounded to low_dtype after
+      every update; the scalars alpha, beta, rho and every dot product are float64;
+    * start: r = b (rounded), x = 0 (float64), x_lo = 0, p = 0, beta = 0, rho = r.r,
+      ||b||^2 = rho, rmax = sqrt(rho);
+    * each iteration of an active right-hand side: p = r + beta p, q = A_low p, alpha = rho / p.q,
+      x_lo += alpha p, r -= alpha q, rho' = r.r; it stops (waits) when sqrt(rho') <= tol ||b||,
+      or at max_iters (not converged); otherwise it asks for an update, and keeps iterating, once
+      sqrt(rho') < delta rmax; then beta = rho' / rho, rho = rho';
+    * the iterations run in chunks of check_every; after each chunk, every right-hand side that
+      asked for an update (or waits after converging) gets one: x += x_lo in float64, x_lo = 0,
+      r64 = b - A x in float64, r = r64 (rounded), rho_t = r64.r64; it is finished when
+      sqrt(rho_t) <= tol ||b||; otherwise beta = rho_t beta / rho (0 with restart_dir: the
+      direction restarts), rho = rho_t, rmax = sqrt(rho_t), and it runs again unless it hit
+      max_iters or its recursive residual converged three updates in a row without the true
+      residual following ("stagnated");
+    * at the end, right-hand sides that stopped without a certified residual get a last fold and
+      float64 residual.
+
+    Columns are independent; a breakdown (p.q <= 0 or non-finite) stops a column as in cg().
+    """
+    B = np.asarray(B, dtype=np.float64)
+    nrhs, n = B.shape
+    X = np.zeros_like(B)
+    xl = np.zeros_like(B)
+    R = _round(B.copy(), low_dtype)
+    P = np.zeros_like(B)
+    rho = np.einsum("ij,ij->i", R, R)
+    tol2 = tol * tol * rho
+    beta = np.zeros(nrhs)
+    rmax = np.sqrt(rho)
+    iters = np.zeros(nrhs, dtype=np.int64)
+    updates = np.zeros(nrhs, dtype=np.int64)
+    fails = np.zeros(nrhs, dtype=np.int64)
+    status: List[Optional[str]] = [None] * nrhs
+    active = np.ones(nrhs, dtype=bool)
+    need = np.zeros(nrhs, dtype=bool)
+    rho_true = rho.copy()
+    for i in range(nrhs):
+        if not np.all(np.isfinite(B[i])):
+            status[i], active[i] = NONFINITE, False
+        elif rho[i] <= tol2[i]:
+            status[i], active[i] = OK, False       # includes b = 0
+    while active.any():
+        for _ in range(check_every):
+            idx = np.nonzero(active)[0]
+            if idx.size == 0:
+                break
+            P[idx] = _round(R[idx] + beta[idx, None] * P[idx], low_dtype)
+            Q = _round(apply_A_low(P[idx]), low_dtype)
+            mu = np.einsum("ij,ij->i", P[idx], Q)
+            for t, i in enumerate(idx):
+                if not (np.isfinite(mu[t]) and mu[t] > 0):
+                    status[i] = NOT_SPD if np.isfinite(mu[t]) else NONFINITE
+                    active[i] = False
+            keep = np.array([active[i] for i in idx], dtype=bool)
+            idx, Q, mu = idx[keep], Q[keep], mu[keep]
+            if idx.size == 0:
+                continue
+            alpha = rho[idx] / mu
+            xl[idx] = _round(xl[idx] + alpha[:, None] * P[idx], low_dtype)
+            R[idx] = _round(R[idx] - alpha[:, None] * Q, low_dtype)
+            rho_new = np.einsum("ij,ij->i", R[idx], R[idx])
+            iters[idx] += 1
+            for t, i in enumerate(idx):
+                if not np.isfinite(rho_new[t]):
+                    status[i], active[i] = NONFINITE, False
+                elif rho_new[t] <= tol2[i]:
+                    need[i], active[i] = True, False
+                elif iters[i] >= max_iters:
+                    status[i], active[i] = NOT_CONVERGED, False
+                elif rho_new[t] < delta * delta * rmax[i] * rmax[i]:
+                    need[i] = True
+            beta[idx] = rho_new / rho[idx]
+            rho[idx] = rho_new
+        for i in np.nonzero(need)[0]:
+            was_active = active[i]
+            X[i] += xl[i]
+            xl[i] = 0.0
+            r64 = B[i] - apply_A64(X[i][None, :])[0]
+            rt = float(r64 @ r64)
+            R[i] = _round(r64, low_dtype)
+            rho_true[i] = rt
+            need[i] = False
+            updates[i] += 1
+            run = False
+            if not np.isfinite(rt):
+                status[i] = NONFINITE
+            elif rt <= tol2[i]:
+                status[i] = OK
+            else:
+                fails[i] = fails[i] + 1 if not was_active else 0
+                if fails[i] >= 3:
+                    status[i] = STAGNATED
+                elif iters[i] >= max_iters:
+                    status[i] = NOT_CONVERGED
+                else:
+                    run = True
+                beta[i] = 0.0 if restart_dir else (rt * beta[i] / rho[i] if rho[i] > 0 else beta[i])
+                rho[i] = rt
+                rmax[i] = np.sqrt(rt)
+            active[i] = run
+    for i in range(nrhs):
+        if status[i] != OK and np.isfinite(B[i]).all():
+            X[i] += xl[i]
+            xl[i] = 0.0
+            r64 = B[i] - apply_A64(X[i][None, :])[0]
+            rho_true[i] = float(r64 @ r64)
+        if status[i] is None:
+            status[i] = NOT_CONVERGED
+    bn2 = np.where(tol2 > 0, tol2 / (tol * tol), 1.0)
+    return ReliableResult(X, iters, updates, status, np.sqrt(rho_true / bn2), np.sqrt(np.maximum(rho, 0) / bn2))
