@@ -601,12 +601,14 @@ def class_model(cls, prec, n, dims, J, has_diag, deferral):
     low-precision MVM and CG update (FP32 working vectors: 4 bytes a word), or None for other classes.
 
     Three-GEMM passes (one term, three 256-wide modes): the direction pass reads r and p_old and writes p
-    and its output (16 B; +8 B when it also takes x += alpha p); the middle pass reads and writes one
-    intermediate (8 B); the last pass reads the intermediate and p and writes q (12 B, +4 B for a
-    diagonal).  Two-GEMM passes (BF16, J terms): the pack reads r, p_old and writes p and its BF16 copy
+    and its output (16 B; +8 B when it also takes x += alpha p: deferral "first", the FP32 engine); the
+    middle pass reads and writes one intermediate (8 B); the last pass reads the intermediate and p and
+    writes q (12 B, +4 B for a diagonal).  Deferral "split" (the BF16x3 engine, all modes 256, the
+    direction in two alternating buffers): the middle and the last pass each take x += alpha p_old on
+    half of x (x and p_old read, x written: +6 B per element each).  Two-GEMM passes (BF16, J terms): the pack reads r, p_old and writes p and its BF16 copy
     (14 B); mode 2 reads the BF16 copy and writes J BF16 intermediates; mode 1 reads them, p (and d) and
     writes q.  The vector update reads x, r, p, q and writes x, r (24 B; 12 B when x is left to the
-    direction pass).  FLOPs are the mode's Table 2 contraction cost times the matrix-core products per
+    GEMM passes).  FLOPs are the mode's Table 2 contraction cost times the matrix-core products per
     useful product."""
     prod = PRODUCTS_PER_FLOP[prec]
     F = len(dims)
@@ -615,7 +617,9 @@ def class_model(cls, prec, n, dims, J, has_diag, deferral):
     if F == 3 and J == 1 and cls.startswith("gemm_mode"):
         m = int(cls[-1])
         fl = 2.0 * n * dims[m - 1] * prod
-        by = {3: 16.0 + (8.0 if deferral else 0.0), 2: 8.0, 1: 12.0 + (4.0 if has_diag else 0.0)}[m]
+        split = 6.0 if deferral == "split" else 0.0
+        by = {3: 16.0 + (8.0 if deferral == "first" else 0.0), 2: 8.0 + split,
+              1: 12.0 + (4.0 if has_diag else 0.0) + split}[m]
         return fl, by * n
     if F == 2 and cls == "gemm_pack":
         return 2.0 * n, 14.0 * n
@@ -681,8 +685,12 @@ def run_single(args, name):
     # algorithmic FLOPs of one RHS*iteration of the working-precision MVM (Table 2 cost, per mode),
     # times the matrix-core products the working precision prescribes per useful product
     flop_rhs_it = 2.0 * n * J * sum(dims) * prod
-    # the FP32 three-GEMM engine takes x += alpha p in its direction pass (reliable-update solves)
-    deferral = prec == "fp32" and name == "c4"
+    # where x += alpha p goes in reliable-update solves (the engine's choice for this operator and precision)
+    deferral = None
+    if name == "c4" and prec == "fp32":
+        deferral = "first"
+    elif name == "c4" and prec == "bf16x3" and all(d == 256 for d in dims):
+        deferral = "split"
     models = {k: class_model(k, prec, n, dims, J, s.diag is not None, deferral) for k in kern}
     models = {k: m for k, m in models.items() if m is not None}
     per_kernel = {}

@@ -347,8 +347,12 @@ int32_t enqueue_mvm(cola_op_s* op, const SysInfo& s, int prec, int nrhs, const v
         g.X = (const float*)X;
         g.R = (const float*)Rpnew;
         // the FP32 engine's direction pass also takes the deferred step x += alpha p_old; the BF16x3
-        // engine leaves x to the vector update
-        g.Xit = (tmpl.epi == EPI_CG && !g.bf16x3) ? (float*)tmpl.Ex : nullptr;
+        // engine (all modes 256) writes the new direction to a second buffer and takes the step in
+        // its middle and last passes, else leaves x to the vector update
+        const bool xsplit = g.bf16x3 && tmpl.epi == EPI_CG && tmpl.Ex && tmpl.Ep2 && g.n1 == kGemm3Tile &&
+                            g.n2 == kGemm3Tile && g.n3 == kGemm3Tile;
+        g.Xit = (tmpl.epi == EPI_CG && (!g.bf16x3 || xsplit)) ? (float*)tmpl.Ex : nullptr;
+        g.P2 = xsplit ? (float*)tmpl.Ep2 : nullptr;
         g.Z1 = (float*)inter[0];
         g.Z2 = (float*)inter[1];
         g.Y = (float*)Yout;
@@ -365,7 +369,7 @@ int32_t enqueue_mvm(cola_op_s* op, const SysInfo& s, int prec, int nrhs, const v
         auto al16 = [](const void* q) { return ((uintptr_t)q & 15) == 0; };
         const bool in_place_p = tmpl.epi != EPI_CG || tmpl.Epout == X;   // the direction is written over p_old
         if (in_place_p && al16(g.K1) && al16(g.K2) && al16(g.K3) && al16(g.X) && al16(g.R) &&
-            al16(g.Xit) && al16(g.Y) && al16(g.dvec)) {
+            al16(g.Xit) && al16(g.P2) && al16(g.Y) && al16(g.dvec)) {
             const char* names[3] = {"gemm_mode3", "gemm_mode2", "gemm_mode1"};
             for (int m = 3; m >= 1; --m) {
                 ProfScope ps(prof, names[3 - m], st);
@@ -504,6 +508,8 @@ int32_t enqueue_iteration(cola_op_s* op, const SysInfo& s, int prec, int nrhs, T
     a.Er = r;
     a.Epout = p;
     a.Ex = defer_x ? x : nullptr;
+    // the direction workspace holds 8 bytes per element: room for a second FP32 direction
+    a.Ep2 = (defer_x && sizeof(T) == 4) ? (void*)(p + (int64_t)nrhs * s.n) : nullptr;
     int32_t rc = enqueue_mvm(op, s, prec, nrhs, p, r, q, a, st);
     if (rc != COLA_OK) return rc;
     ProfScope ps(op->prof, sizeof(T) == 8 ? "update_fp64" : "update", st);
@@ -521,6 +527,7 @@ struct ReliableTail {
     float* xl;        // low-precision iterate
     float* rl;        // low-precision residual
     const float* pl;  // low-precision direction (a deferred x += alpha p is caught up from it)
+    const float* pl2; // its second buffer (the engines that alternate two direction buffers)
 };
 
 // final == false: the reliable update of the right-hand sides that asked for
@@ -534,7 +541,7 @@ int32_t enqueue_tail(cola_op_s* op, const SysInfo& s, int nrhs, const ReliableTa
     TraceRange trace_range(final ? "reliable_final" : "reliable_update");
     Workspace& w = op->ws;
     if (final) HIP_TRY(mark_unverified(w.cg, nrhs, st));
-    HIP_TRY(reliable_fold<float>(t.X, t.xl, t.pl, s.n, nrhs, w.cg, false, st));
+    HIP_TRY(reliable_fold<float>(t.X, t.xl, t.pl, t.pl2, s.n, nrhs, w.cg, false, st));
     PassArgs a = base_args(op);
     a.cg = w.cg;
     a.gate = &w.cg->need_update;
@@ -1038,7 +1045,7 @@ int32_t solve_system(cola_op_s* op, const SysInfo& s, const double* B, double* X
         const double delta = (op->prec == COLA_PREC_BF16) ? -o->inner_tol : o->inner_tol;
         HIP_TRY(cg_prepare<float>(warm ? w.r64 : w.b64, rl, xl, pl, n, nrhs, nullptr, w.cg, o->tol, o->max_iters,
                                   delta, w.partials, ps, w.counters, w.cnt, st, false, warm));
-        ReliableTail tail{w.x64, w.b64, xl, rl, pl};
+        ReliableTail tail{w.x64, w.b64, xl, rl, pl, pl + (int64_t)nrhs * n};
         int32_t rc = run_cg<float>(op, s, op->prec, nrhs, xl, rl, pl, ql, o->max_iters, o->check_every, &tail, st);
         if (rc != COLA_OK) return rc;
         rc = enqueue_tail(op, s, nrhs, tail, true, st);       // final fold and true residual where stale

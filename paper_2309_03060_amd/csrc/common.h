@@ -37,6 +37,9 @@ struct CgState {
     int32_t restart_dir; // reliable updates restart the direction (p = r) instead of keeping it
     int32_t xdefer;    // x += alpha p is applied by the next iteration's first MVM pass, not the update
     int32_t xlag;      // (xdefer) x still lacks alpha p of the last step taken
+    int32_t pbuf;      // which of two direction buffers holds the current p (pswap engines)
+    int32_t pswap;     // the first MVM pass writes the new direction to the other buffer; the
+                       // vector update then flips pbuf
 };
 
 // Refinement (outer) state, one per RHS.

@@ -37,6 +37,8 @@ struct PassArgs {
     const void* Er;       // CG: r;      RESID: b
     void* Epout;          // CG: p_new
     void* Ex;             // CG: the iterate, when the first pass may apply x += alpha p_old (else null)
+    void* Ep2;            // CG with Ex: a second direction buffer an engine may alternate with Epout
+                          // (pbuf / pswap of the CG state), else null
     const void* dvec;     // diagonal d (vector element type), may be null
     double sigma2;
 

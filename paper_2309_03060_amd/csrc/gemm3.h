@@ -19,6 +19,9 @@ struct Gemm3Args {
     const float* R;           // CG: r
     float* Xit;               // CG with reliable updates: the iterate; the first pass applies the
                               // previous step's x += alpha p_old (deferred from the update), else null
+    float* P2;                // BF16x3 CG with Xit, all modes 256: second direction buffer.  The first
+                              // pass reads p_old from buffer pbuf and writes p_new to the other one;
+                              // the middle and last passes take x += alpha p_old (half of x each)
     float* Z1; float* Z2;     // intermediates, nrhs * n1 * n2 * n3 each
     float* Y;                 // q
     const float* dvec;        // n or null
@@ -32,6 +35,10 @@ struct Gemm3Args {
 };
 
 bool gemm3_supported(int prec, int Fv, int J, const int64_t* dims);
+
+// Tile edge of the engine (n3 always equals it); the double-buffered direction of the BF16x3
+// engine needs every mode equal to it.
+constexpr int kGemm3Tile = 256;
 
 // Enqueue one pass: mode 3, 2 or 1 (in that order).
 hipError_t launch_gemm3(const Gemm3Args& a, int mode, hipStream_t s);

@@ -318,14 +318,21 @@ struct FacSet {
     floatx4 f[2];
 };
 
-// The direction pass (PNEW) leaves x += alpha p to the vector update: taking that step here
-// (as the FP32 engine does) was measured slower, this pass being bound by its memory traffic.
+// The direction pass (PNEW) leaves x += alpha p to the other passes: taking that step here (as
+// the FP32 engine does) was measured slower, this pass being bound by its memory traffic.  With
+// a second direction buffer (Gemm3Args::P2) p_old survives the direction pass, and the middle
+// and last passes, bound by their MFMAs, each take the step on half of x: 4 elements per thread
+// and k slice, loaded before the slice's MFMAs (after the factor, before the next slice's vector
+// loads, so the latter stay in flight) and stored after them.
 template <bool PNEW>
 struct X3Thread {
     const float* A;      // this thread's vector row, at its k chunk
     const float* R;      // PNEW: residual
     float* P;            // PNEW: direction written back
     const float* F;      // this thread's factor row (FP32), at its k chunk
+    float* XU;           // deferred step: this thread's 4 elements of x for k slice 0, else null
+    const float* PU;     // p_old at the same elements
+    float xalpha;
     double beta;
     uint32_t sdst;       // byte offset of this thread's chunk in a plane
     uint32_t afr, bfr;   // fragment offsets (factor tile 0, vector tile 0)
@@ -351,7 +358,10 @@ struct X3Thread {
             for (int h = 0; h < 2; ++h) {
 #pragma unroll
                 for (int c = 0; c < 4; ++c) v[h][c] = pnew_of(o.r[h][c], v[h][c], beta);
-                *(floatx4*)(P + k0 + 4 * h) = v[h];
+                // streamed past the caches: no other pass of this MVM reads p before the last
+                // pass's epilogue, and keeping it out of the L2 and the last-level cache leaves them
+                // to the other passes' operands
+                __builtin_nontemporal_store(v[h], (floatx4*)(P + k0 + 4 * h));
             }
         }
         bf16x8 hp, mp, lp;
@@ -386,18 +396,30 @@ struct X3Thread {
                     for (int j = 0; j < 2; ++j) acc[i][j] = mfma_bf16(fv[i], vv[s][j], acc[i][j]);
         }
     }
-    // one k slice: when LOAD start slice kl's loads into ld, multiply the slice in stage S, when
-    // STORE split slice ks (held in st) into stage T
+    // one k slice (the c-th): when LOAD start slice kl's loads into ld, multiply the slice in
+    // stage S, when STORE split slice ks (held in st) into stage T; with XU take the deferred step
+    // on the c-th chunk of this thread's share of x
     template <bool LOAD, bool STORE>
     __device__ __attribute__((always_inline)) void step(floatx16 (&acc)[4][2], const char* S, char* T,
                                                         OpSet<PNEW>& ld, const OpSet<PNEW>& st, int kl,
-                                                        int ks) const {
+                                                        int ks, int c) const {
         FacSet fs;
+        floatx4 xv = {}, pv = {};
+        const int64_t xo = (int64_t)c * XT * 4;
         if constexpr (STORE) load_fac(ks, fs);
+        if (XU) {                                          // streamed: read and written once
+            xv = __builtin_nontemporal_load((const floatx4*)(XU + xo));
+            pv = __builtin_nontemporal_load((const floatx4*)(PU + xo));
+        }
         if constexpr (LOAD) load(kl, ld);
         __builtin_amdgcn_sched_barrier(0);                 // keep the loads ahead of the MFMAs
         compute(acc, S);
         if constexpr (STORE) store(ks, T, st, fs);
+        if (XU) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) xv[u] = __builtin_fmaf(xalpha, pv[u], xv[u]);
+            __builtin_nontemporal_store(xv, (floatx4*)(XU + xo));
+        }
     }
 };
 
@@ -420,12 +442,34 @@ __global__ __launch_bounds__(XT) void k_gemm3x3(Gemm3Args a, PassDesc d) {
     // staging: thread t covers row t / 2, k chunk t % 2 (8 values) of each slice, of both operands
     const int srow = tid >> 1, schunk = tid & 1;
     const int64_t sofs = (m0 + srow) * K + 8 * schunk;
+    // double-buffered direction (CG only): p_old in buffer pbuf, p_new in the other one
+    const int cur = a.P2 ? a.cg[r].pbuf : 0;
+    const float* const pold_b = cur ? a.P2 : a.X;
+    float* const pnew_b = a.P2 ? (cur ? const_cast<float*>(a.X) : a.P2) : const_cast<float*>(a.X);
     X3Thread<PNEW> th;
-    th.A = d.A + sofs;
+    th.A = (PNEW ? pold_b : d.A) + sofs;
     th.R = PNEW ? d.R + sofs : nullptr;
-    th.P = PNEW ? d.Pout + sofs : nullptr;
+    th.P = PNEW ? pnew_b + sofs : nullptr;
     th.F = d.B + (int64_t)(n0 + srow) * K + 8 * schunk;
     th.beta = PNEW ? a.cg[r].beta : 0.0;
+    th.XU = nullptr;
+    th.PU = nullptr;
+    th.xalpha = 0.f;
+    if constexpr (PNEW) {
+        if (a.P2 && threadIdx.x == 0) {                    // every block stores the same values
+            a.cg[r].pswap = 1;
+            a.cg[r].xdefer = 1;
+        }
+    } else if (a.P2 && a.Xit && a.cg[r].xlag) {
+        // the middle pass steps the first half of x, the last pass the second; each block its
+        // 128 K elements of the half (one N tile per row band: every mode is 256)
+        const int64_t nr = d.rows_per_rhs * K;
+        const int64_t o = (int64_t)r * nr + (EPI == EPI_CG ? nr / 2 : 0) +
+                          (m0 - (int64_t)r * d.rows_per_rhs) / 2 * K + 4 * tid;
+        th.XU = a.Xit + o;
+        th.PU = pold_b + o;
+        th.xalpha = (float)a.cg[r].alpha;
+    }
     th.sdst = (uint32_t)(srow * XROW + 16 * (schunk ^ x3_swz(srow)));
     // fragment reads: row (lane % 32) of each 32-row tile, logical chunk lane / 32
     const uint32_t flane = (uint32_t)((lane & 31) * XROW + 16 * ((lane >> 5) ^ x3_swz(lane & 31)));
@@ -456,14 +500,14 @@ __global__ __launch_bounds__(XT) void k_gemm3x3(Gemm3Args a, PassDesc d) {
     // register sets count exactly and the loads of slice ks + 2 stay in flight across the barrier.
     int ks = 0;
     for (; ks + 2 < ns; ks += 2) {
-        th.template step<true, true>(acc, st0, st1, R0, R1, (ks + 2) * XKS, (ks + 1) * XKS);
+        th.template step<true, true>(acc, st0, st1, R0, R1, (ks + 2) * XKS, (ks + 1) * XKS, ks);
         lds_barrier();
-        th.template step<true, true>(acc, st1, st0, R1, R0, (ks + 3) * XKS, (ks + 2) * XKS);
+        th.template step<true, true>(acc, st1, st0, R1, R0, (ks + 3) * XKS, (ks + 2) * XKS, ks + 1);
         lds_barrier();
     }
-    th.template step<false, true>(acc, st0, st1, R0, R1, 0, (ks + 1) * XKS);
+    th.template step<false, true>(acc, st0, st1, R0, R1, 0, (ks + 1) * XKS, ks);
     lds_barrier();
-    th.template step<false, false>(acc, st1, st0, R1, R0, 0, 0);
+    th.template step<false, false>(acc, st1, st0, R1, R0, 0, 0, ks + 1);
 
     // epilogue straight from the accumulators: element v of tile (i, j) is output column
     // n0 + wn*128 + 32 i + row32(lane, v), entry (local row) + wm*64 + 32 j + lane % 32; the
@@ -473,7 +517,8 @@ __global__ __launch_bounds__(XT) void k_gemm3x3(Gemm3Args a, PassDesc d) {
     const int64_t lane_pos = (int64_t)(n0 + wn * 128 + 4 * (lane >> 5)) * rpr +
                              (m0 - (int64_t)r * rpr) + wm * 64 + (lane & 31);
     float* const out = d.Out + (int64_t)r * d.N * rpr + lane_pos;
-    const float* const xin = EPI == EPI_STORE ? nullptr : a.X + (int64_t)r * d.N * rpr + lane_pos;
+    // the last pass reads p_new (CG) or x (product)
+    const float* const xin = EPI == EPI_STORE ? nullptr : pnew_b + (int64_t)r * d.N * rpr + lane_pos;
     const float* const dgv = a.dvec ? a.dvec + lane_pos : nullptr;
     const float s2 = (float)a.sigma2;
     double dacc[4] = {0.0, 0.0, 0.0, 0.0};                 // p.q in FP64, four short chains

@@ -29,8 +29,8 @@ hipError_t rhs_norm2(const double* B, int64_t n, int nrhs, CgState* cg, double* 
                      uint32_t* counters, hipStream_t s);
 
 template <typename T>
-hipError_t reliable_fold(double* x64, T* xlo, const T* p, int64_t n, int nrhs, const CgState* cg, bool all_rhs,
-                         hipStream_t s);
+hipError_t reliable_fold(double* x64, T* xlo, const T* p, const T* p2, int64_t n, int nrhs, const CgState* cg,
+                         bool all_rhs, hipStream_t s);
 
 template <typename T>
 hipError_t reliable_apply(const double* r64, T* rlo, int64_t n, int nrhs, CgState* cg, double* partials,

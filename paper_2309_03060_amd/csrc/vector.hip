@@ -133,6 +133,8 @@ __global__ __launch_bounds__(kThreads) void k_cg_prepare(const double* src, T* r
         st.updates = 0;
         st.xdefer = 0;
         st.xlag = 0;
+        st.pbuf = 0;
+        st.pswap = 0;
         if (!finite_d(tot)) {
             st.status = COLA_ERR_NONFINITE;
             st.active = 0;
@@ -236,6 +238,7 @@ __global__ __launch_bounds__(kThreads) void k_cg_update(T* x, T* r, const T* p, 
         CgState& st = cg[g];
         st.iters += 1;
         if (st.xdefer) st.xlag = 1;                      // x now lacks alpha p of this step
+        if (st.pswap) st.pbuf ^= 1;                      // this step's direction is in the other buffer
         if (hist && st.iters <= hist_len) {      // the CG coefficients behind the Lanczos tridiagonal
             double* h = hist + ((int64_t)g * hist_len + st.iters - 1) * 2;
             h[0] = st.alpha;
@@ -299,9 +302,10 @@ __global__ void k_outer_bookkeep(OuterState* outer, const CgState* cg, int nrhs,
 // Reliable update, step 1 (gated on need_update, or every RHS when
 // all_rhs): fold the low-precision iterate into the FP64 solution, x_lo = 0.
 // An iterate whose last step is still deferred (xlag) gets alpha p first, in
-// the working precision, as the vector update would have applied it.
+// the working precision, as the vector update would have applied it (p from
+// the second direction buffer p2 when pbuf says so).
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_reliable_fold(double* x64, T* xlo, const T* p, int64_t n,
+__global__ __launch_bounds__(kThreads) void k_reliable_fold(double* x64, T* xlo, const T* p, const T* p2, int64_t n,
                                                             const CgState* cg, int all_rhs) {
     const int64_t g = blockIdx.y;
     if (!all_rhs && !cg[g].need_update) return;
@@ -309,7 +313,8 @@ __global__ __launch_bounds__(kThreads) void k_reliable_fold(double* x64, T* xlo,
     T* lg = xlo + g * n;
     const bool lag = p && cg[g].xlag;
     const T alpha = (T)cg[g].alpha;
-    const T* pg = p ? p + g * n : nullptr;
+    const T* pb = (p2 && cg[g].pbuf) ? p2 : p;
+    const T* pg = pb ? pb + g * n : nullptr;
     for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
         const T v = lag ? fmat(alpha, pg[i], lg[i]) : lg[i];
         xg[i] += (double)v;
@@ -459,14 +464,14 @@ hipError_t rhs_norm2(const double* B, int64_t n, int nrhs, CgState* cg, double* 
 }
 
 template <typename T>
-hipError_t reliable_fold(double* x64, T* xlo, const T* p, int64_t n, int nrhs, const CgState* cg, bool all_rhs,
-                         hipStream_t s) {
+hipError_t reliable_fold(double* x64, T* xlo, const T* p, const T* p2, int64_t n, int nrhs, const CgState* cg,
+                         bool all_rhs, hipStream_t s) {
     dim3 grid(vec_blocks_per_rhs(n), nrhs);
-    hipLaunchKernelGGL(k_reliable_fold<T>, grid, dim3(kThreads), 0, s, x64, xlo, p, n, cg, all_rhs ? 1 : 0);
+    hipLaunchKernelGGL(k_reliable_fold<T>, grid, dim3(kThreads), 0, s, x64, xlo, p, p2, n, cg, all_rhs ? 1 : 0);
     return hipGetLastError();
 }
-template hipError_t reliable_fold<float>(double*, float*, const float*, int64_t, int, const CgState*, bool,
-                                         hipStream_t);
+template hipError_t reliable_fold<float>(double*, float*, const float*, const float*, int64_t, int, const CgState*,
+                                         bool, hipStream_t);
 
 template <typename T>
 hipError_t reliable_apply(const double* r64, T* rlo, int64_t n, int nrhs, CgState* cg, double* partials,

@@ -99,12 +99,14 @@ def test_refined_fp32_dense_gemm3_path():
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
 @pytest.mark.parametrize("iters", [1, 6, 40])
 def test_gemm3_deferred_iterate_at_iteration_limit(iters, prec):
-    """The FP32 three-GEMM engine applies x += alpha p one iteration late (in its first pass).  A solve
-    stopped by the iteration limit must still contain its last step, also after reliable updates (the
-    fold catches a pending step up, the update clears the flag, the next iteration resumes the
-    deferral): the same solve on the contraction passes (x updated at once) agrees to FP32 rounding,
-    while a dropped or doubled step would differ by O(1); both are certified by the oracle's FP64
-    residual of the returned X.  The BF16x3 engine (x updated at once) is held to the same check."""
+    """The three-GEMM engines apply x += alpha p one iteration late: the FP32 engine in its first
+    pass, the BF16x3 engine (the direction alternating between two buffers) half in its middle and
+    half in its last pass.  A solve stopped by the iteration limit must still contain its last step,
+    also after reliable updates (the fold catches a pending step up from the right buffer, the update
+    clears the flag, the next iteration resumes the deferral): the same solve on the contraction
+    passes (x updated at once) agrees to FP32 rounding, while a dropped or doubled step, or a step
+    taken from the wrong buffer, would differ by O(1); both are certified by the oracle's FP64
+    residual of the returned X."""
     from gpu_util import infos, make_op, pack, unpack
     rng = np.random.default_rng(97)
     s = wl.random_system(rng, (256, 256, 256), nterms=1, diag=False, sigma2=0.5)
