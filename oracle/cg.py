@@ -190,6 +190,11 @@ def refine(apply_A64: Callable, apply_A_low: Callable, B: np.ndarray, tol: float
     return RefineResult(X, sweeps, inner, status, rel, hist)
 
 
+# Reliable updates: a recursive residual below this fraction of the last true residual is taken as
+# the working precision's noise floor (the right-hand side waits for its update there).
+NOISE_FLOOR = 1e-5
+
+
 @dataclass
 class ReliableResult:
     X: np.ndarray
@@ -213,14 +218,16 @@ def reliable(apply_A64: Callable, apply_A_low: Callable, B: np.ndarray, tol: flo
     * each iteration of an active right-hand side: p = r + beta p, q = A_low p, alpha = rho / p.q,
       x_lo += alpha p, r -= alpha q, rho' = r.r; it stops (waits) when sqrt(rho') <= tol ||b||,
       or at max_iters (not converged); otherwise it asks for an update, and keeps iterating, once
-      sqrt(rho') < delta rmax; then beta = rho' / rho, rho = rho';
+      sqrt(rho') < delta rmax, unless sqrt(rho') < NOISE_FLOOR rmax, where it waits for the update
+      (that far below the last true residual the working-precision recursion is rounding noise);
+      then beta = rho' / rho, rho = rho';
     * the iterations run in chunks of check_every; after each chunk, every right-hand side that
       asked for an update (or waits after converging) gets one: x += x_lo in float64, x_lo = 0,
       r64 = b - A x in float64, r = r64 (rounded), rho_t = r64.r64; it is finished when
       sqrt(rho_t) <= tol ||b||; otherwise beta = rho_t beta / rho (0 with restart_dir: the
       direction restarts), rho = rho_t, rmax = sqrt(rho_t), and it runs again unless it hit
       max_iters or its recursive residual converged three updates in a row without the true
-      residual following ("stagnated");
+      residual following ("stagnated"; a wait at the noise floor is no convergence);
     * at the end, right-hand sides that stopped without a certified residual get a last fold and
       float64 residual.
 
@@ -243,6 +250,7 @@ def reliable(apply_A64: Callable, apply_A_low: Callable, B: np.ndarray, tol: flo
     active = np.ones(nrhs, dtype=bool)
     need = np.zeros(nrhs, dtype=bool)
     rho_true = rho.copy()
+    noise = np.zeros(nrhs, dtype=bool)
     for i in range(nrhs):
         if not np.all(np.isfinite(B[i])):
             status[i], active[i] = NONFINITE, False
@@ -278,6 +286,8 @@ def reliable(apply_A64: Callable, apply_A_low: Callable, B: np.ndarray, tol: flo
                     status[i], active[i] = NOT_CONVERGED, False
                 elif rho_new[t] < delta * delta * rmax[i] * rmax[i]:
                     need[i] = True
+                    if rho_new[t] < NOISE_FLOOR * NOISE_FLOOR * rmax[i] * rmax[i]:
+                        noise[i], active[i] = True, False
             beta[idx] = rho_new / rho[idx]
             rho[idx] = rho_new
         for i in np.nonzero(need)[0]:
@@ -296,7 +306,7 @@ def reliable(apply_A64: Callable, apply_A_low: Callable, B: np.ndarray, tol: flo
             elif rt <= tol2[i]:
                 status[i] = OK
             else:
-                fails[i] = fails[i] + 1 if not was_active else 0
+                fails[i] = fails[i] + 1 if not (was_active or noise[i]) else 0
                 if fails[i] >= 3:
                     status[i] = STAGNATED
                 elif iters[i] >= max_iters:
@@ -307,6 +317,7 @@ def reliable(apply_A64: Callable, apply_A_low: Callable, B: np.ndarray, tol: flo
                 rho[i] = rt
                 rmax[i] = np.sqrt(rt)
             active[i] = run
+            noise[i] = False
     for i in range(nrhs):
         if status[i] != OK and np.isfinite(B[i]).all():
             X[i] += xl[i]

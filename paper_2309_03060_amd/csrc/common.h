@@ -31,7 +31,8 @@ struct CgState {
     int32_t iters;
     int32_t status;    // COLA_* numerical status of this solve
     int32_t max_iters;
-    int32_t need_update; // reliable update requested for the end of this chunk
+    int32_t need_update; // reliable update requested for the end of this chunk (kNoisePause: and
+                         // paused until then, the recursion being at its noise floor)
     int32_t fails;     // consecutive reliable updates after which the true residual missed tol
     int32_t updates;   // reliable updates done
     int32_t restart_dir; // reliable updates restart the direction (p = r) instead of keeping it
@@ -41,6 +42,16 @@ struct CgState {
     int32_t pswap;     // the first MVM pass writes the new direction to the other buffer; the
                        // vector update then flips pbuf
 };
+
+// Reliable updates: a right-hand side whose recursive residual has fallen below kNoiseFloor
+// times its last true residual stops iterating until the update at the end of its chunk
+// (need_update = kNoisePause).  That far down, the FP32 recursion's residual and direction are
+// made of rounding noise (orthogonality to the previous direction is lost), and further steps on
+// them can make the residual grow without bound, e.g. for a right-hand side that is an
+// eigenvector of the operator, whose residual is at the noise floor after one step.  A right-hand
+// side falls this far within one chunk only when it converges that fast.
+constexpr double kNoiseFloor = 1e-5;
+constexpr int32_t kNoisePause = 2;
 
 // Refinement (outer) state, one per RHS.
 struct OuterState {
@@ -216,6 +227,7 @@ __device__ inline void outer_residual(OuterState& o, double tot, SolveCounters* 
 __device__ inline void reliable_finish(CgState& st, SolveCounters* cnt) {
     const double rt = st.rho_true;
     const bool was_active = st.active != 0;
+    const bool noise_pause = st.need_update == kNoisePause;
     st.need_update = 0;
     st.updates += 1;
     bool run = false;
@@ -224,7 +236,8 @@ __device__ inline void reliable_finish(CgState& st, SolveCounters* cnt) {
     } else if (rt <= st.tol2) {
         st.status = COLA_OK;
     } else {
-        if (!was_active) st.fails += 1;       // recursive residual converged, true one did not
+        // recursive residual converged, true one did not (a noise-floor pause is no convergence)
+        if (!was_active && !noise_pause) st.fails += 1;
         else st.fails = 0;
         if (st.fails >= 3) st.status = COLA_STAGNATED;
         else if (st.iters >= st.max_iters) st.status = COLA_NOT_CONVERGED;

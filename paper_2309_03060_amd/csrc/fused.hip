@@ -454,7 +454,13 @@ __global__ __launch_bounds__(kFT) void k_fused_cg(FusedCgArgs a) {
                 fs.status = COLA_NOT_CONVERGED;
             } else {
                 stop = false;
-                if (delta > 0.0 && tot < delta * delta * rmax * rmax) fs.need_update = 1;
+                if (delta > 0.0 && tot < delta * delta * rmax * rmax) {
+                    fs.need_update = 1;
+                    if (tot < kNoiseFloor * kNoiseFloor * rmax * rmax) {
+                        fs.need_update = kNoisePause;
+                        stop = true;
+                    }
+                }
             }
             fs.beta = tot / fs.rho;
             fs.rho = tot;

@@ -257,7 +257,13 @@ __global__ __launch_bounds__(kThreads) void k_cg_update(T* x, T* r, const T* p, 
             st.status = COLA_NOT_CONVERGED;
         } else {
             stop = false;
-            if (st.delta > 0.0 && tot < st.delta * st.delta * st.rmax * st.rmax) st.need_update = 1;
+            if (st.delta > 0.0 && tot < st.delta * st.delta * st.rmax * st.rmax) {
+                st.need_update = 1;
+                if (tot < kNoiseFloor * kNoiseFloor * st.rmax * st.rmax) {
+                    st.need_update = kNoisePause;
+                    stop = true;
+                }
+            }
         }
         st.beta = tot / st.rho;
         st.rho = tot;

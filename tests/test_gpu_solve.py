@@ -129,6 +129,41 @@ def test_gemm3_deferred_iterate_at_iteration_limit(iters, prec):
         assert abs(i["relres"] - r) <= 1e-3 * r + 1e-15
 
 
+@pytest.mark.parametrize("tol", [1e-5, 1e-9])
+def test_gemm3_direction_buffers_per_rhs(tol):
+    """The BF16x3 engine keeps each right-hand side's direction in one of two buffers, flipped every
+    iteration it takes.  A right-hand side that is an eigenvector of the operator (b = u1 (x) u2 (x) u3)
+    has its recursive residual at rounding level after one step and pauses there (tol 1e-5: certified
+    at once; tol 1e-9: the FP64 residual resumes it), while the random ones keep iterating, so their
+    buffers part in parity.  Every right-hand side must come out as from the contraction passes (x
+    updated at once): the same iteration counts up to the drift of a different summation order, the
+    solutions equal to the tolerance's forward error, all certified by the oracle's FP64 residual."""
+    from gpu_util import infos, make_op, pack, unpack
+    rng = np.random.default_rng(99)
+    s = wl.random_system(rng, (256, 256, 256), nterms=1, diag=False, sigma2=0.5)
+    u = [np.linalg.eigh(f)[1][:, -1 - k] for k, f in enumerate(s.factors[0])]
+    B = rng.standard_normal((3, s.n))
+    B[1] = np.einsum("a,b,c->abc", *u).reshape(-1) * 3.0
+    out = []
+    for gemm3 in (True, False):
+        op = make_op([s], prec="bf16x3")
+        op.set_engine("gemm3", gemm3)
+        X, info = op.solve(pack([B]), 3, tol=tol, max_iters=2000, prec="bf16x3", inner_tol=0.1, check_every=4)
+        out.append((unpack(X, [s], 3)[0], infos(info, 3)))
+        op.close()
+    (Xg, ig), (Xc, ic) = out
+    rr = kron.relres(s.factors, Xg, B, s.sigma2)
+    for k in range(3):
+        assert ig[k]["status"] == 0 and ic[k]["status"] == 0, (ig, ic)
+        assert abs(ig[k]["iters"] - ic[k]["iters"]) <= max(2, ic[k]["iters"] // 20), (ig, ic)
+        assert rr[k] <= tol and abs(ig[k]["relres"] - rr[k]) <= 1e-3 * rr[k], (rr, ig)
+    assert ig[1]["iters"] < ig[0]["iters"] and ig[1]["iters"] < ig[2]["iters"], ig
+    ev = [np.linalg.eigvalsh(f) for f in s.factors[0]]
+    kappa = (np.prod([e.max() for e in ev]) + s.sigma2) / (np.prod([e.min() for e in ev]) + s.sigma2)
+    for k in range(3):
+        assert np.linalg.norm(Xg[k] - Xc[k]) <= 4 * kappa * tol * np.linalg.norm(Xc[k]), k
+
+
 @pytest.mark.parametrize("iters", [1, 5])
 def test_gemm2_deferred_iterate_at_iteration_limit(iters):
     """The BF16 two-GEMM engine stopped at the iteration limit agrees with the BF16 contraction passes

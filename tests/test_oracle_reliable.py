@@ -4,7 +4,9 @@ The paper prints no mixed-precision scheme; the oracle writes out the reading th
 These tests tie that reading to what mathematics fixes: without rounding it is textbook CG (a
 residual replacement changes nothing then), with float32 vectors it reaches float64 accuracy where
 plain float32 CG cannot, it replaces the residual once per factor delta of reduction, and an
-inconsistent low-precision operator makes it stagnate.
+inconsistent low-precision operator makes it stagnate.  Right-hand sides that converge within a
+chunk (an eigenvector of the operator: one exact CG step) must not run on past the working
+precision's noise floor, whatever the chunk length.
 """
 import numpy as np
 import pytest
@@ -103,3 +105,48 @@ def test_edge_cases_and_stagnation():
     kept = cg.reliable(lambda V: 2.0 * V, lambda V: 4.5 * V, Bs, tol=1e-10, delta=0.1, max_iters=200,
                        check_every=1, low_dtype=None)
     assert kept.status[0] in ("stagnated", "not_converged") and kept.relres_true[0] > 1e-10
+
+
+@pytest.mark.parametrize("every", [1, 4, 32])
+def test_eigenvector_rhs_converges_at_any_chunk_length(every):
+    """b = 3 u1 (x) u2 (x) u3 with u_k eigenvectors of the factors: exact CG ends after one step with
+    x = b / lambda.  In float32 the recursive residual is then at rounding level, and steps taken on
+    it are noise; the right-hand side waits for its update there, so for every chunk length the
+    solve reaches 1e-9 within a few iterations and returns b / lambda (forward error within
+    kappa tol).  A random right-hand side beside it is unaffected (the same iterations to one)."""
+    rng = np.random.default_rng(99)
+    s = wl.random_system(rng, (16, 16, 16), nterms=1, diag=False, sigma2=0.5)
+    pairs = [np.linalg.eigh(f) for f in s.factors[0]]
+    u = [v[:, -1 - k] for k, (_, v) in enumerate(pairs)]
+    lam = float(np.prod([w[-1 - k] for k, (w, _) in enumerate(pairs)])) + s.sigma2
+    B = rng.standard_normal((2, s.n))
+    B[1] = 3.0 * np.einsum("a,b,c->abc", *u).reshape(-1)
+    low = [[lowprec.to_fp32(f) for f in s.factors[0]]]
+    A64 = lambda V: kron.mvm(s.factors, V, s.sigma2)
+    Alo = lambda V: kron.mvm(low, V, float(np.float32(s.sigma2)))
+    res = cg.reliable(A64, Alo, B, tol=1e-9, delta=0.1, max_iters=2000, check_every=every)
+    ref = cg.reliable(A64, Alo, B, tol=1e-9, delta=0.1, max_iters=2000, check_every=1)
+    assert res.status == ["ok", "ok"], (res.status, res.iters)
+    assert res.iters[1] <= 12, res.iters
+    assert abs(int(res.iters[0]) - int(ref.iters[0])) <= 1
+    ev = [w for w, _ in pairs]
+    kappa = (np.prod([e.max() for e in ev]) + s.sigma2) / (np.prod([e.min() for e in ev]) + s.sigma2)
+    x = B[1] / lam
+    assert np.linalg.norm(res.X[1] - x) <= kappa * 1e-9 * np.linalg.norm(x)
+
+
+def test_fast_solves_with_long_chunks_track_textbook_cg():
+    """A system solved in ~45 iterations with 32-iteration chunks: each chunk's recursion would run
+    far past the noise floor; waiting there keeps the iteration count within a few of textbook CG
+    (running on gave 231 / 542 / 381 iterations before the rule)."""
+    rng = np.random.default_rng(7002)
+    s = wl.random_system(rng, (12, 10), nterms=2, diag=True, sigma2=0.2)
+    B = rng.standard_normal((3, s.n))
+    low = [[lowprec.to_fp32(f) for f in row] for row in s.factors]
+    A64 = lambda V: kron.mvm(s.factors, V, s.sigma2, s.diag)
+    Alo = lambda V: kron.mvm(low, V, float(np.float32(s.sigma2)), lowprec.to_fp32(s.diag))
+    ref = cg.cg(A64, B, tol=1e-10, max_iters=500)
+    res = cg.reliable(A64, Alo, B, tol=1e-10, delta=0.1, max_iters=3000, check_every=32)
+    assert res.status == ["ok"] * 3
+    assert np.all(res.iters <= ref.iters + 4), (res.iters, ref.iters)
+    assert np.all(kron.relres(s.factors, res.X, B, s.sigma2, s.diag) <= 1e-10)
