@@ -212,7 +212,11 @@ typedef struct {
  *    residual <= tol.  refine == COLA_REFINE_RELIABLE (default): a single CG in
  *    the working precision whose x is folded into the FP64 solution and whose
  *    residual is replaced by the FP64 one every time it has dropped by
- *    inner_tol (or has converged), keeping the search direction.
+ *    inner_tol (or has converged), keeping the search direction; the
+ *    replacement comes at the end of the check_every chunk in which the drop
+ *    happened, and a right-hand side whose recursive residual falls below
+ *    1e-5 of its last FP64 one stops iterating until then (its FP32
+ *    recursion is rounding noise that far down).
  *    refine == COLA_REFINE_RESTART: each sweep solves A d = r / ||r|| from
  *    scratch to inner_tol and updates x += ||r|| d in FP64.
  * Right-hand sides converge independently; the call ends when all have
