@@ -822,7 +822,11 @@ def run_single(args, name):
             "config": {"workload": label + (" (+ adjoint backward per step)" if G is not None else ""), "n": n,
                        "nrhs": nrhs, "window_iters": window, "rhs_iters_per_step": rhs_iters // max(1, args.steps),
                        "reliable_update_delta": delta if prec != "fp64" else None,
-                       "statuses": statuses, "worst_relres": worst, "parallelism": "single GPU"},
+                       "statuses": statuses, "worst_relres": worst, "parallelism": "single GPU",
+                       **({"window_note": "statuses and worst_relres are those of a window of CG iterations from "
+                                          "x0 = 0 (stopped by the iteration limit; the FP64 true residual can exceed "
+                                          "the initial one there, CG residual norms not being monotone); the solve "
+                                          "to the target is mixed_vs_fp64"} if window else {})},
             "roofline": roof, "cpu_baseline": cpu, "mixed_vs_fp64": tts, "direct_eig_solve": direct,
             "other_workloads": extra}
 
