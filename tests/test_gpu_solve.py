@@ -164,6 +164,41 @@ def test_gemm3_direction_buffers_per_rhs(tol):
         assert np.linalg.norm(Xg[k] - Xc[k]) <= 4 * kappa * tol * np.linalg.norm(Xc[k]), k
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_gemm3_cg_with_diagonal(prec):
+    """The three-GEMM engines' CG epilogue with a diagonal d (q = K p + (sigma2 + d) p, then p.q),
+    with the BF16x3 engine's alternating direction: a solve to 1e-9 certified by the oracle's FP64
+    residual, within the forward-error bound of the contraction passes' solution, iteration counts
+    within the drift of a different summation order; and the same solve stopped at 7 iterations
+    agreeing with the contraction passes to FP32 rounding."""
+    from gpu_util import infos, make_op, pack, unpack
+    rng = np.random.default_rng(101)
+    s = wl.random_system(rng, (256, 256, 256), nterms=1, diag=True, sigma2=0.3)
+    B = rng.standard_normal((2, s.n))
+    res = {}
+    for gemm3 in (True, False):
+        for tol, mi in ((1e-9, 3000), (1e-12, 7)):
+            op = make_op([s], prec=prec)
+            op.set_engine("gemm3", gemm3)
+            X, info = op.solve(pack([B]), 2, tol=tol, max_iters=mi, prec=prec, inner_tol=0.1)
+            res[(gemm3, mi)] = (unpack(X, [s], 2)[0], infos(info, 2))
+            op.close()
+    (Xg, ig), (Xc, ic) = res[(True, 3000)], res[(False, 3000)]
+    rr = kron.relres(s.factors, Xg, B, s.sigma2, s.diag)
+    ev = [np.linalg.eigvalsh(f) for f in s.factors[0]]
+    lo = np.prod([e.min() for e in ev]) + s.sigma2 + s.diag.min()
+    hi = np.prod([e.max() for e in ev]) + s.sigma2 + s.diag.max()
+    for k in range(2):
+        assert ig[k]["status"] == 0 and ic[k]["status"] == 0, (ig, ic)
+        assert rr[k] <= 1e-9 and abs(ig[k]["relres"] - rr[k]) <= 1e-3 * rr[k], (rr, ig)
+        assert abs(ig[k]["iters"] - ic[k]["iters"]) <= max(2, ic[k]["iters"] // 20), (ig, ic)
+        assert np.linalg.norm(Xg[k] - Xc[k]) <= 4 * (hi / lo) * 1e-9 * np.linalg.norm(Xc[k])
+    (Xg, ig), (Xc, ic) = res[(True, 7)], res[(False, 7)]
+    for i in ig + ic:
+        assert i["status"] == 1 and i["iters"] == 7, i
+    assert np.abs(Xg - Xc).max() <= 1e-4 * np.abs(Xc).max()
+
+
 @pytest.mark.parametrize("iters", [1, 5])
 def test_gemm2_deferred_iterate_at_iteration_limit(iters):
     """The BF16 two-GEMM engine stopped at the iteration limit agrees with the BF16 contraction passes
