@@ -121,3 +121,23 @@ def test_unrolled_baselines_match_oracle_on_cpu():
     ld = bench.unrolled_slq_logdet(K, s2, torch.tensor(Z).reshape(3, 6, 6, 6), 7)
     ref = slq.slq_logdet(lambda M: kron.mvm([facs], M, s2), Z, 7)
     assert abs(float(ld) - ref) <= 1e-10 * abs(ref)
+
+
+def test_class_model_bytes_per_engine_layout():
+    """Algorithmic bytes per element of the three-GEMM launch classes (one term, three 256-wide
+    modes), each following its reads and writes: 60 B per element and iteration with x in the
+    update or split over the middle and last passes, 56 B with x in the direction pass (which
+    holds p_old already, so the update no longer reads p)."""
+    n, dims = 256 ** 3, [256, 256, 256]
+    by = {}
+    for deferral in (None, "first", "split"):
+        by[deferral] = {c: bench.class_model(c, "bf16x3", n, dims, 1, False, deferral)[1] / n
+                        for c in ("gemm_mode3", "gemm_mode2", "gemm_mode1", "update")}
+    assert by[None] == {"gemm_mode3": 16, "gemm_mode2": 8, "gemm_mode1": 12, "update": 24}
+    assert by["first"] == {"gemm_mode3": 24, "gemm_mode2": 8, "gemm_mode1": 12, "update": 12}
+    assert by["split"] == {"gemm_mode3": 16, "gemm_mode2": 14, "gemm_mode1": 18, "update": 12}
+    assert sum(by[None].values()) == 60 and sum(by["split"].values()) == 60
+    assert sum(by["first"].values()) == 56
+    # the diagonal adds its read to the last pass; FLOPs count the six BF16x3 products per useful one
+    fl, b = bench.class_model("gemm_mode1", "bf16x3", n, dims, 1, True, "split")
+    assert b / n == 22 and fl == 2.0 * n * 256 * 6
