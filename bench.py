@@ -844,7 +844,8 @@ def other_workloads(args):
         out[wname] = {"workload": r["config"]["workload"], "value": r["value"], "unit": r["unit"],
                       "ms_per_step": r["ms_per_step"], "dtype": r["dtype"], "steps": a.steps,
                       "worst_relres": r["config"].get("worst_relres"), "statuses": r["config"].get("statuses"),
-                      "roofline": {k: roof.get(k) for k in ("kernel", "bound", "achieved", "peak", "unit", "frac")}}
+                      "roofline": {k: roof.get(k) for k in ("kernel", "bound", "achieved", "peak", "unit", "frac",
+                                                              "traffic")}}
         progress(f"extra workload {wname}: {r['value']} RHS*iters/s")
     return out
 
