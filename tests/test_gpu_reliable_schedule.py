@@ -1,4 +1,4 @@
-"""The library's reliable-update schedule against the oracle's (oracle.cg.reliable).
+"""The library's mixed-precision schedules against the oracle's (oracle.cg.reliable, oracle.cg.refine).
 
 Both sides follow one reading of the paper's low precision by algorithmic modification (Sec. 3.4,
 App. C.3): a single FP32 CG whose residual is replaced by the FP64 true residual b - A x once it has
@@ -8,6 +8,9 @@ chunks are of one iteration).  The two differ only in the FP32 summation order o
 on well-conditioned systems the iteration counts agree to a few, the number of replacements to one
 and the status exactly, and both solutions are certified by the FP64 residual and agree within the
 forward-error bound.  Each case checks, from the profile classes, that the engine named ran.
+Restarted refinement (refine="restart") is compared the same way with oracle.cg.refine: each sweep
+an FP32 CG from zero on r / ||r|| to inner_tol, then x += ||r|| d in FP64; the same status and
+number of sweeps, inner iterations summed over the sweeps within a few.
 """
 import numpy as np
 import pytest
@@ -157,3 +160,55 @@ def test_schedule_64cube(engine, every, chunk, cls):
     op.close()
     assert n >= 1, (engine, cls)
     _compare(s, B, X, rec, _W64[key], tol, iter_band=6)
+
+
+def _refine_oracle(s, B, tol, inner_tol, max_sweeps, max_iters):
+    A64 = lambda V: kron.mvm(s.factors, V, s.sigma2, s.diag)
+    return ocg.refine(A64, _low(s), B, tol=tol, inner_tol=inner_tol, max_sweeps=max_sweeps,
+                      inner_max_iters=max_iters)
+
+
+def _compare_refine(s, B, X, rec, ref, tol, iter_band):
+    rr = kron.relres(s.factors, X, B, s.sigma2, s.diag)
+    kappa = _cond(s)
+    for i in range(B.shape[0]):
+        assert rec[i]["status"] == 0 and ref.status[i] == "ok", (rec[i], ref.status[i])
+        assert rec[i]["sweeps"] == int(ref.sweeps[i]), (i, rec[i], ref.sweeps)
+        assert abs(rec[i]["iters"] - int(ref.inner_iters[i])) <= iter_band, (i, rec[i], ref.inner_iters)
+        assert rr[i] <= tol and abs(rec[i]["relres_true"] - rr[i]) <= 1e-3 * rr[i], (rr, rec[i])
+        xn = np.linalg.norm(ref.X[i])
+        assert np.linalg.norm(X[i] - ref.X[i]) <= 4.0 * kappa * tol * xn, (i, kappa)
+
+
+@pytest.mark.parametrize("inner_tol", [1e-2, 1e-3, 1e-5])
+def test_restart_schedule_small(inner_tol):
+    """Two-term two-mode system with a diagonal on the contraction passes (4-8 sweeps of ~10-25
+    inner iterations)."""
+    from gpu_util import make_op
+    rng = np.random.default_rng(7002)
+    s = wl.random_system(rng, (12, 10), nterms=2, diag=True, sigma2=0.2)
+    B = rng.standard_normal((3, s.n))
+    tol = 1e-10
+    op = make_op([s], prec="fp32")
+    kw = dict(tol=tol, max_iters=3000, inner_tol=inner_tol, max_sweeps=20, check_every=4, refine="restart")
+    X, rec = _solve(op, s, B, **kw)
+    op.close()
+    _compare_refine(s, B, X, rec, _refine_oracle(s, B, tol, inner_tol, 20, 3000), tol, iter_band=3)
+
+
+def test_restart_schedule_64cube_fused():
+    """The 64^3 Wishart operator on the persistent fused CG (inner solves without reliable updates):
+    3 sweeps of ~90 inner iterations to 1e-8."""
+    from gpu_util import make_op
+    s, B = _w64()
+    tol, inner_tol = 1e-8, 1e-3
+    key = ("refine", inner_tol)
+    if key not in _W64:
+        _W64[key] = _refine_oracle(s, B, tol, inner_tol, 20, 3000)
+    op = make_op([s], prec="fp32")
+    kw = dict(tol=tol, max_iters=3000, inner_tol=inner_tol, max_sweeps=20, check_every=16, refine="restart")
+    X, rec = _solve(op, s, B, **kw)
+    n = _launches(op, s, B, "cg_fused", **kw)
+    op.close()
+    assert n >= 1
+    _compare_refine(s, B, X, rec, _W64[key], tol, iter_band=6)
