@@ -41,7 +41,14 @@ def _cond(s):
         hi = np.prod([e.max() for e in ev]) + s.sigma2
         lo = np.prod([e.min() for e in ev]) + s.sigma2
         return float(hi / lo)
-    return float(np.linalg.cond(kron.dense_operator(s.factors, s.sigma2, s.diag)))
+    if s.n <= 4096:
+        return float(np.linalg.cond(kron.dense_operator(s.factors, s.sigma2, s.diag)))
+    # a bound (Weyl): the Kronecker terms are PSD, each at most the product of its factors' largest
+    # eigenvalues
+    top = sum(np.prod([np.linalg.eigvalsh(f).max() for f in row]) for row in s.factors)
+    dmin = 0.0 if s.diag is None else float(s.diag.min())
+    dmax = 0.0 if s.diag is None else float(s.diag.max())
+    return float((top + s.sigma2 + dmax) / (s.sigma2 + dmin))
 
 
 def _compare(s, B, X, rec, ref, tol, iter_band):
@@ -212,3 +219,60 @@ def test_restart_schedule_64cube_fused():
     op.close()
     assert n >= 1
     _compare_refine(s, B, X, rec, _W64[key], tol, iter_band=6)
+
+
+def _bf16_two_gemm_low(s):
+    """The BF16 two-GEMM engine's product as the oracle emulates it: BF16 factors, the direction's
+    BF16 copy in the first GEMM, its output T rounded to BF16 before the second, the diagonal term
+    on the FP32 direction; sums in FP64 (the engine's FP32 accumulation order is the difference)."""
+    n1, n2 = (f.shape[0] for f in s.factors[0])
+    U = [lowprec.to_bf16(row[0]) for row in s.factors]
+    V = [lowprec.to_bf16(row[1]) for row in s.factors]
+    dd = float(np.float32(s.sigma2)) + (0.0 if s.diag is None else lowprec.to_fp32(s.diag))
+
+    def apply(P):
+        out = np.empty_like(P)
+        P16 = lowprec.to_bf16(P)
+        for i in range(P.shape[0]):
+            X = P16[i].reshape(n1, n2)
+            y = sum(u @ lowprec.to_bf16(X @ v.T) for u, v in zip(U, V))
+            out[i] = y.reshape(-1) + dd * P[i]
+        return out
+    return apply
+
+
+@pytest.mark.parametrize("every", [8, 32])
+def test_bf16_restart_direction_schedule(every):
+    """Plain BF16 working precision restarts the direction at every replacement (the rounded
+    operator is too coarse for the old one): the two-GEMM engine against oracle.cg.reliable with
+    restart_dir and the engine's roundings emulated (52-84 iterations, 4-7 replacements)."""
+    from gpu_util import make_op
+    rng = np.random.default_rng(7010)
+    s = wl.random_system(rng, (256, 256), nterms=2, diag=True, sigma2=0.3)
+    B = rng.standard_normal((2, s.n))
+    tol = 1e-8
+    op = make_op([s], prec="bf16")
+    kw = dict(tol=tol, max_iters=2000, inner_tol=0.1, check_every=every)
+    import torch
+    from gpu_util import infos, pack, unpack
+    X, info = op.solve(pack([B]), 2, prec="bf16", **kw)
+    torch.cuda.synchronize()
+    X, rec = unpack(X, [s], 2)[0], infos(info, 2)
+    n = _launches_prec(op, s, B, "gemm_mode1", "bf16", **kw)
+    op.close()
+    assert n >= 1
+    A64 = lambda V: kron.mvm(s.factors, V, s.sigma2, s.diag)
+    ref = ocg.reliable(A64, _bf16_two_gemm_low(s), B, tol=tol, delta=0.1, max_iters=2000, check_every=every,
+                       restart_dir=True)
+    _compare(s, B, X, rec, ref, tol, iter_band=3)
+
+
+def _launches_prec(op, s, B, cls, prec, **kw):
+    import torch
+    from gpu_util import pack
+    op.profile_enable(True)
+    op.solve(pack([B]), B.shape[0], prec=prec, **kw)
+    torch.cuda.synchronize()
+    n = op.profile_read(cls)[1]
+    op.profile_enable(False)
+    return n
