@@ -273,6 +273,57 @@ def _launches_prec(op, s, B, cls, prec, **kw):
     op.profile_enable(True)
     op.solve(pack([B]), B.shape[0], prec=prec, **kw)
     torch.cuda.synchronize()
-    n = op.profile_read(cls)[1]
+    n = sum(op.profile_read(c)[1] for c in ((cls,) if isinstance(cls, str) else cls))
     op.profile_enable(False)
     return n
+
+
+def _bf16x3_contraction_low(s):
+    """BF16x3 mode products as the oracle emulates them: every factor and every pass's input split
+    three ways (v = h + m + l, each part the BF16 rounding of the remainder), the six leading cross
+    products summed, each pass's output rounded to FP32, modes from the last to the first."""
+    dims = [f.shape[0] for f in s.factors[0]]
+    F = [[lowprec.bf16_split(f, 3) for f in row] for row in s.factors]
+    dd = float(np.float32(s.sigma2)) + (0.0 if s.diag is None else lowprec.to_fp32(s.diag))
+
+    def mode(T, parts, k):
+        tp = lowprec.bf16_split(T, 3)
+        out = 0.0
+        for fi in range(3):
+            for ti in range(3 - fi):
+                out = out + np.moveaxis(np.tensordot(tp[ti], parts[fi], axes=([k + 1], [1])), -1, k + 1)
+        return lowprec.to_fp32(out)
+
+    def apply(P):
+        out = np.zeros_like(P)
+        for row in F:
+            T = P.reshape((P.shape[0],) + tuple(dims))
+            for k in reversed(range(len(dims))):
+                T = mode(T, row[k], k)
+            out += T.reshape(P.shape[0], -1)
+        return out + dd * P
+    return apply
+
+
+@pytest.mark.parametrize("every", [1, 16])
+def test_bf16x3_schedule_contraction_passes(every):
+    """BF16x3 working precision on the general contraction passes (a 40 x 36 x 32 operator with a
+    diagonal, ~140 iterations to 1e-9) against oracle.cg.reliable with the split products emulated."""
+    from gpu_util import make_op
+    rng = np.random.default_rng(7020)
+    s = wl.random_system(rng, (40, 36, 32), nterms=1, diag=True, sigma2=0.1)
+    B = rng.standard_normal((2, s.n))
+    tol = 1e-9
+    op = make_op([s], prec="bf16x3")
+    kw = dict(tol=tol, max_iters=3000, inner_tol=0.1, check_every=every)
+    import torch
+    from gpu_util import infos, pack, unpack
+    X, info = op.solve(pack([B]), 2, prec="bf16x3", **kw)
+    torch.cuda.synchronize()
+    X, rec = unpack(X, [s], 2)[0], infos(info, 2)
+    n = _launches_prec(op, s, B, _CONTRACT, "bf16x3", **kw)
+    op.close()
+    assert n >= 1
+    A64 = lambda V: kron.mvm(s.factors, V, s.sigma2, s.diag)
+    ref = ocg.reliable(A64, _bf16x3_contraction_low(s), B, tol=tol, delta=0.1, max_iters=3000, check_every=every)
+    _compare(s, B, X, rec, ref, tol, iter_band=4)
